@@ -1,0 +1,277 @@
+"""Seeded synthetic initial states for the HEVI dynamical-core step.
+
+This module only *builds inputs*: vertical levels, hydrostatic reference
+columns, warm bubbles, velocity noise and the named workload shapes.  It holds
+none of the time-stepping arithmetic.  The CPU oracle and the GPU library both
+take these arrays as inputs, and neither imports the other.
+
+The paper runs its model on real JMA analyses (Sect. 4: a 301x301x58 grid and
+the 1581x1301x58 production grid at 2 km).  Those data are not available, so
+the states below stand in for them: a stretched 20 km column, an isothermal
+hydrostatic atmosphere, warm bubbles and Gaussian velocity noise in a uniform
+wind.  Every random number comes from a counter-based generator (splitmix64
+of the seed, the field id and the cell index, then Box-Muller), so any
+sub-block of a field can be regenerated without drawing the rest.
+
+Layout: canonical i-fastest.  Cell fields have shape (nz, ny, nx); the
+vertical momentum lives on the nz+1 level faces, shape (nz+1, ny, nx).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, List, Optional
+
+import numpy as np
+
+# Physical constants of the synthetic atmosphere (SI units).
+R_DRY = 287.04
+CP_DRY = 3.5 * R_DRY
+KAPPA = 2.0 / 7.0
+GRAV = 9.80665
+P00 = 1.0e5
+H_TOP = 20000.0
+
+FIELD_NAMES = ("rho_ptb", "rhou", "rhov", "rhow", "rhotheta_ptb")
+
+
+# --------------------------------------------------------------------------
+# counter-based random numbers
+# --------------------------------------------------------------------------
+_M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def splitmix64(x: np.ndarray) -> np.ndarray:
+    """splitmix64 finaliser (Steele, Lea & Flood 2014) on uint64 arrays."""
+    z = np.asarray(x, dtype=np.uint64).copy()
+    with np.errstate(over="ignore"):
+        z = z + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def _uniform01(bits: np.ndarray) -> np.ndarray:
+    """Map 64 random bits to a double in (0, 1]."""
+    return ((bits >> np.uint64(11)).astype(np.float64) + 1.0) * (1.0 / 9007199254740992.0)
+
+
+def gaussian(seed: int, component: int, shape, offset=(0, 0, 0), full=None) -> np.ndarray:
+    """i.i.d. N(0,1) values indexed by (seed, component, k, j, i).
+
+    ``shape`` is (nk, nj, ni); ``offset`` shifts the (k, j, i) counters so a
+    sub-block reproduces the same numbers as the whole field would; ``full`` is
+    the (nz, ny, nx) extent the counters are numbered over (defaults to shape).
+    """
+    nk, nj, ni = shape
+    full = shape if full is None else full
+    k = np.arange(nk, dtype=np.uint64)[:, None, None] + np.uint64(offset[0])
+    j = np.arange(nj, dtype=np.uint64)[None, :, None] + np.uint64(offset[1])
+    i = np.arange(ni, dtype=np.uint64)[None, None, :] + np.uint64(offset[2])
+    with np.errstate(over="ignore"):
+        base = splitmix64(np.uint64(seed & 0xFFFFFFFFFFFFFFFF) * np.uint64(0x100000001B3)
+                          + np.uint64(component))
+        ctr = base + (k * np.uint64(full[1]) + j) * np.uint64(full[2]) + i
+    b1 = splitmix64(ctr)
+    b2 = splitmix64(ctr ^ np.uint64(0xD1B54A32D192ED03))
+    u1 = _uniform01(b1)
+    u2 = _uniform01(b2)
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * math.pi * u2)
+
+
+# --------------------------------------------------------------------------
+# vertical grid and reference columns
+# --------------------------------------------------------------------------
+def levels(nz: int, top: float = H_TOP) -> np.ndarray:
+    """Stretched level faces zeta_k = H (s + s^2)/2, s = k/nz (nz+1 values)."""
+    s = np.arange(nz + 1, dtype=np.float64) / nz
+    z = top * (s + s * s) / 2.0
+    z[0] = 0.0
+    z[-1] = top
+    return z
+
+
+def uniform_levels(nz: int, top: float) -> np.ndarray:
+    return np.linspace(0.0, top, nz + 1)
+
+
+def centres(zf: np.ndarray) -> np.ndarray:
+    return 0.5 * (zf[1:] + zf[:-1])
+
+
+def reference_isothermal(zc: np.ndarray, t0: float = 300.0, p0: float = 1.0e5):
+    """Hydrostatic isothermal atmosphere at the given heights.
+
+    Returns (rho_ref, rhotheta_ref, p_ref): p = p0 exp(-z/Hs), Hs = R T0 / g,
+    rho = p / (R T0), theta = T0 (P00/p)^kappa, rhotheta = rho * theta.
+    """
+    hs = R_DRY * t0 / GRAV
+    p = p0 * np.exp(-zc / hs)
+    rho = p / (R_DRY * t0)
+    theta = t0 * (P00 / p) ** KAPPA
+    return rho, rho * theta, p
+
+
+def reference_neutral(zc: np.ndarray, theta0: float = 300.0):
+    """Hydrostatic atmosphere of uniform potential temperature theta0."""
+    exner = 1.0 - GRAV * zc / (CP_DRY * theta0)
+    p = P00 * exner ** (CP_DRY / R_DRY)
+    rho = p / (R_DRY * exner * theta0)
+    return rho, rho * theta0, p
+
+
+def reference_uniform(nz: int, rho0: float = 1.0, theta0: float = 300.0, gamma: float = 1.4):
+    """Height-independent reference (only consistent for g = 0 test cases)."""
+    rho = np.full(nz, rho0)
+    rt = rho * theta0
+    p = P00 * (R_DRY * rt / P00) ** gamma
+    return rho, rt, p
+
+
+# --------------------------------------------------------------------------
+# states
+# --------------------------------------------------------------------------
+@dataclasses.dataclass
+class State:
+    """One synthetic domain: grid description, reference columns, fields."""
+    nx: int
+    ny: int
+    nz: int
+    dx: float
+    dy: float
+    zf: np.ndarray
+    rho_ref: np.ndarray
+    rt_ref: np.ndarray
+    p_ref: np.ndarray
+    fields: List[np.ndarray]          # rho', U, V, W, Theta' (float64, canonical)
+    dt: float = 10.0
+    n_short: int = 4
+    n_long: int = 10
+    beta: float = 0.55
+    name: str = ""
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def copy(self) -> "State":
+        return dataclasses.replace(self, fields=[f.copy() for f in self.fields])
+
+    def as_f32(self) -> "State":
+        """The same state with every field rounded to binary32 (kept as float64)."""
+        return dataclasses.replace(
+            self, fields=[f.astype(np.float32).astype(np.float64) for f in self.fields])
+
+
+def _periodic_dist(x: np.ndarray, xc: float, length: float) -> np.ndarray:
+    d = np.abs(x - xc)
+    return np.minimum(d, length - d)
+
+
+def bubble_theta(nx, ny, zc, dx, dy, bubbles, amp=2.0) -> np.ndarray:
+    """Sum of cos^2 warm bubbles: amp * cos^2(pi r / 2) for r < 1.
+
+    ``bubbles`` is a list of (xc, yc, zc, radius); r is the 3D distance
+    (periodic in x and y) divided by the radius.
+    """
+    lx, ly = nx * dx, ny * dy
+    x = (np.arange(nx) + 0.5) * dx
+    y = (np.arange(ny) + 0.5) * dy
+    th = np.zeros((len(zc), ny, nx))
+    for (xb, yb, zb, rb) in bubbles:
+        ddx = _periodic_dist(x, xb, lx)[None, None, :]
+        ddy = _periodic_dist(y, yb, ly)[None, :, None]
+        ddz = (zc - zb)[:, None, None]
+        r = np.sqrt(ddx * ddx + ddy * ddy + ddz * ddz) / rb
+        th += np.where(r < 1.0, amp * np.cos(0.5 * math.pi * np.minimum(r, 1.0)) ** 2, 0.0)
+    return th
+
+
+def random_bubbles(seed: int, count: int, lx: float, ly: float,
+                   rmin=2000.0, rmax=8000.0, ztop=12000.0):
+    """count bubbles: radius ~ U[rmin, rmax], x, y ~ U[0, L), z ~ U[r + 500 m, ztop]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        rb = rng.uniform(rmin, rmax)
+        xb = rng.uniform(0.0, lx)
+        yb = rng.uniform(0.0, ly)
+        zb = rng.uniform(rb + 500.0, ztop)
+        out.append((xb, yb, zb, rb))
+    return out
+
+
+def make_state(nx: int, ny: int, nz: int, dx: float = 2000.0, dy: float = 2000.0,
+               seed: int = 1710, bubbles: Optional[list] = None, u_bg: float = 10.0,
+               v_bg: float = 0.0, noise: float = 0.1, dt: float = 10.0, n_short: int = 4,
+               n_long: int = 10, beta: float = 0.55, zf: Optional[np.ndarray] = None,
+               reference: str = "isothermal", name: str = "") -> State:
+    """Warm-bubble state at constant pressure in a uniform wind plus noise.
+
+    Theta' = 0 and rho' = rhotheta_ref / (theta_ref + theta_bubble) - rho_ref,
+    so the pressure is the reference pressure everywhere.  U = rho_u (u_bg + n)
+    with rho_u the two-point mean density on the x-face and n ~ N(0, noise^2);
+    V likewise; W = rho_w n on interior faces and 0 on the lids.
+    """
+    zf = levels(nz) if zf is None else np.asarray(zf, dtype=np.float64)
+    zc = centres(zf)
+    if reference == "isothermal":
+        rho_ref, rt_ref, p_ref = reference_isothermal(zc)
+    elif reference == "neutral":
+        rho_ref, rt_ref, p_ref = reference_neutral(zc)
+    else:
+        raise ValueError(reference)
+    th_ref = rt_ref / rho_ref
+    if bubbles is None:
+        bubbles = [(0.5 * nx * dx, 0.5 * ny * dy, 5000.0, 4000.0)]
+    thb = bubble_theta(nx, ny, zc, dx, dy, bubbles)
+    rho_full = rt_ref[:, None, None] / (th_ref[:, None, None] + thb)
+    rho_p = rho_full - rho_ref[:, None, None]
+    rt_p = np.zeros((nz, ny, nx))
+    rho_u = 0.5 * (np.roll(rho_full, 1, axis=2) + rho_full)
+    rho_v = 0.5 * (np.roll(rho_full, 1, axis=1) + rho_full)
+    U = rho_u * (u_bg + noise * gaussian(seed, 0, (nz, ny, nx)))
+    V = rho_v * (v_bg + noise * gaussian(seed, 1, (nz, ny, nx)))
+    dz = np.diff(zf)
+    W = np.zeros((nz + 1, ny, nx))
+    if nz > 1:
+        a = dz[:-1] / (dz[:-1] + dz[1:])           # weight of the cell above face k
+        b = dz[1:] / (dz[:-1] + dz[1:])            # weight of the cell below face k
+        rho_w = a[:, None, None] * rho_full[1:] + b[:, None, None] * rho_full[:-1]
+        W[1:nz] = rho_w * noise * gaussian(seed, 2, (nz + 1, ny, nx))[1:nz]
+    return State(nx, ny, nz, dx, dy, zf, rho_ref, rt_ref, p_ref,
+                 [rho_p, U, V, W, rt_p], dt=dt, n_short=n_short, n_long=n_long,
+                 beta=beta, name=name)
+
+
+def rest_state(nx, ny, nz, dx=2000.0, dy=2000.0, zf=None, reference="isothermal",
+               **kw) -> State:
+    zf = levels(nz) if zf is None else zf
+    zc = centres(zf)
+    ref = reference_isothermal(zc) if reference == "isothermal" else reference_neutral(zc)
+    f = [np.zeros((nz, ny, nx)), np.zeros((nz, ny, nx)), np.zeros((nz, ny, nx)),
+         np.zeros((nz + 1, ny, nx)), np.zeros((nz, ny, nx))]
+    return State(nx, ny, nz, dx, dy, zf, ref[0], ref[1], ref[2], f, **kw)
+
+
+# --------------------------------------------------------------------------
+# named workloads
+# --------------------------------------------------------------------------
+def workload(name: str) -> State:
+    """The synthetic single-domain workloads used by tests and the benchmark.
+
+    small       64x64x32, dx = 2 km, one bubble (r = 4 km, centre 5 km), FP64 run
+                of 10 long steps with 4 short steps per stage, dt = 10 s.
+    large       1024x1024x64, 16 bubbles (r in 2..8 km), 100 long steps, n = 6.
+    large_sub   128x128x64 sub-run of the same generator (oracle-sized).
+    """
+    if name == "small":
+        return make_state(64, 64, 32, seed=1710, dt=10.0, n_short=4, n_long=10, name=name)
+    if name in ("large", "large_sub"):
+        n = 1024 if name == "large" else 128
+        seed = 1711
+        bub = random_bubbles(seed, 16, n * 2000.0, n * 2000.0)
+        return make_state(n, n, 64, seed=seed, bubbles=bub, dt=10.0, n_short=6,
+                          n_long=100, name=name)
+    raise KeyError(name)

@@ -1,0 +1,131 @@
+/*
+ * hevi.h -- C ABI of the HEVI dynamical-core step on AMD Instinct (gfx950).
+ *
+ * The operation: one long time step of a compressible, non-hydrostatic
+ * dynamical core on a 3D structured grid, as outlined in the paper's
+ * Sect. 1.1 ("ASUCA on GPU"): finite-volume discretisation, a third-order
+ * Runge-Kutta long step (Wicker & Skamarock 2002), and horizontally-explicit /
+ * vertically-implicit (HEVI) short steps for sound and gravity waves, with the
+ * vertical coupling solved as one tridiagonal system per column.  Prognostic
+ * density and rho*theta are stored as perturbations on a reference column, as
+ * the paper's Listing 1 does for density (Sect. 2.1).  The paper's device data
+ * region model (Sect. 2.2, "Device Data Region": copy in once at the start,
+ * copy out at output, nothing in between) is the shape of this interface.
+ *
+ * Conventions
+ *  - Host arrays are float64 in canonical i-fastest order, index
+ *    i + nx*(j + ny*k).  Cell fields have nx*ny*nz values; the vertical
+ *    momentum rho*w has nx*ny*(nz+1) values (level faces 0..nz), and its
+ *    two lid levels must be 0.  U = rho*u sits on the west face of cell i,
+ *    V = rho*v on the south face of cell j; the domain is periodic in x and y.
+ *  - Host pointers are borrowed for the duration of the call only.
+ *  - Device memory: the caller owns one workspace of at least
+ *    hv_workspace_bytes() bytes (any device allocation, 256-byte aligned);
+ *    the library carves all its device arrays out of it and allocates no
+ *    device memory of its own.
+ *  - Streams: every launch goes to the hipStream_t given at creation.
+ *    hv_step only enqueues work; hv_state_read and hv_mass synchronise the
+ *    stream.
+ *  - Errors: every int-returning call returns HV_OK (0) or a negative code;
+ *    hv_last_error(handle) gives a text (hv_last_error(NULL) the text of the
+ *    last failure of a call that had no valid handle).  No C++ exception
+ *    crosses the ABI.  A handle is not thread-safe; distinct handles may be
+ *    used from distinct threads.
+ */
+#ifndef HEVI_H
+#define HEVI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hv_grid *hv_grid_t;
+
+enum {
+    HV_OK = 0,
+    HV_ERR_ARG = -1,          /* invalid argument, size, shape or workspace   */
+    HV_ERR_HIP = -2,          /* a HIP runtime call failed (see hv_last_error)*/
+    HV_ERR_STATE = -3,        /* step/read/mass before hv_state_init          */
+    HV_ERR_NONFINITE = -4,    /* the FP64 mass sum is not finite              */
+    HV_ERR_UNSUPPORTED = -5   /* valid request this build does not implement  */
+};
+
+/* Arithmetic of the stencil sweeps / of the column solve and global sums:
+ * HV_FP64  float64 / float64,
+ * HV_FP32  float32 / float32 (mass sums still float64),
+ * HV_MIXED float32 storage and sweeps / float64 vertical solve and sums. */
+enum { HV_FP64 = 0, HV_FP32 = 1, HV_MIXED = 2 };
+
+/* Device storage order.  HV_KIJ (column-fastest, k + nz*(i + nx*j)) is the
+ * layout the kernels are built around; HV_IJK (i-fastest) runs the same
+ * kernels with strided column access, for layout comparisons. */
+enum { HV_IJK = 0, HV_KIJ = 1 };
+
+/* Field ids for hv_state_read. */
+enum { HV_RHO_PTB = 0, HV_RHOU = 1, HV_RHOV = 2, HV_RHOW = 3, HV_RHOTHETA_PTB = 4 };
+
+typedef struct {
+    int32_t nx, ny, nz;        /* cells; nx, ny >= 4; nz in {32, 64, 128}    */
+    double dx, dy;             /* horizontal spacing (m), > 0                */
+    const double *zeta_faces;  /* nz+1 increasing level heights, [0] = 0     */
+    const double *terrain;     /* must be NULL: flat lower boundary          */
+    int32_t precision;         /* HV_FP64 / HV_FP32 / HV_MIXED               */
+    int32_t layout;            /* HV_KIJ or HV_IJK                           */
+    double beta;               /* off-centring of the vertical solve, in [0.5, 1] */
+    double div_damp;           /* must be 0                                  */
+} hv_grid_desc;
+
+/* Bytes of device workspace the grid needs; 0 if the description is invalid
+ * (the reason is then in hv_last_error(NULL)).  Host-only, no HIP call. */
+size_t hv_workspace_bytes(const hv_grid_desc *desc);
+
+/* Create a grid.  dev_workspace: caller-owned device memory of `bytes`
+ * bytes (>= hv_workspace_bytes), kept alive until hv_grid_destroy.
+ * hip_stream: a hipStream_t (NULL = the default stream).  On success *out
+ * receives the handle. */
+int hv_grid_create(const hv_grid_desc *desc, void *dev_workspace, size_t bytes,
+                   void *hip_stream, hv_grid_t *out);
+
+/* Load a state (the paper's copy-in at the start of a run).  fields[f] for
+ * f = HV_RHO_PTB..HV_RHOTHETA_PTB as described above; rho_ref, rhotheta_ref
+ * and p_ref are the reference columns at the nz cell centres.  Values are
+ * converted to the grid's precision and layout.  Non-finite input, or a
+ * non-zero rho*w on a lid, returns HV_ERR_ARG.  Synchronises the stream. */
+int hv_state_init(hv_grid_t g, const double *const fields[5], const double *rho_ref,
+                  const double *rhotheta_ref, const double *p_ref);
+
+/* Enqueue n_long RK3 long steps of length dt (s) with n_short HEVI short
+ * steps per stage (stage lengths dt/3, dt/2, dt; each stage restarts its
+ * short steps from the state at the start of the long step).  After every
+ * long step the total mass is summed in float64.  Asynchronous: faults and
+ * non-finite mass surface at the next hv_state_read / hv_mass. */
+int hv_step(hv_grid_t g, double dt, int32_t n_long, int32_t n_short);
+
+/* Copy one field back to the host in canonical float64 layout (the paper's
+ * copy-out at output time).  host_out holds nx*ny*nz values, or
+ * nx*ny*(nz+1) for HV_RHOW.  Synchronises the stream. */
+int hv_state_read(hv_grid_t g, int32_t field, double *host_out);
+
+/* Total mass sum (rho_ref + rho') dx dy dz and the diagnostic total energy
+ * (kinetic + internal + potential) of the current state, in float64 with a
+ * fixed summation order.  Either output pointer may be NULL.  Returns
+ * HV_ERR_NONFINITE if the mass after any step so far is not finite.
+ * Synchronises the stream. */
+int hv_mass(hv_grid_t g, double *mass_out, double *energy_out);
+
+/* Release the handle (never the caller's workspace).  NULL is a no-op. */
+void hv_grid_destroy(hv_grid_t g);
+
+/* Text of the last failure on this handle (or, for NULL, of the last
+ * failure that had no valid handle).  Never NULL; valid until the next call
+ * on the same handle. */
+const char *hv_last_error(hv_grid_t g);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HEVI_H */

@@ -1,0 +1,952 @@
+// hevi_kernels.hip -- HIP kernels of the HEVI dynamical-core step for gfx950.
+//
+// Work mapping.  A column (i, j) of nz cells is owned by one 16-lane segment
+// of a 64-lane wavefront; lane p of the segment owns the L = nz/16 consecutive
+// levels k0 = p*L .. k0+L-1.  In the column-fastest layout those L values are
+// contiguous, so each per-lane access is one vector load and a wavefront
+// touches 4 columns of contiguous memory.  Vertical neighbours live in the
+// adjacent lane of the same segment (segment shuffles); horizontal neighbours
+// are other columns and come through L1/L2.  A block of 256 threads covers 16
+// consecutive columns.
+//
+// The per-column tridiagonal system of the vertically implicit part is solved
+// without leaving the segment: every lane eliminates its interior rows in
+// terms of the last unknown of the lane below and its own last unknown; the
+// remaining 16-row system of those interface unknowns is solved by parallel
+// cyclic reduction over the segment (4 steps), and the interior values follow.
+//
+// Equations: the paper (Sect. 1.1) fixes finite volumes, an RK3 long step
+// after Wicker & Skamarock (2002) and HEVI short steps; the discrete form
+// implemented here is:
+//  slow sweep, once per stage on the stage-input state
+//    u = U / (mean of rho over the x-face), v likewise, w = W / (rho linearly
+//    interpolated to the level face); theta = Theta / rho;
+//    S_U = -div(m q) over the U control volume with mass fluxes m averaged
+//    from U, V, W and q the Koren (kappa = 1/3) face value of u; S_V, S_W
+//    likewise; R_Theta = -div(m (Koren face theta - centred face theta));
+//    p'_s = p_ref expm1(gamma log1p(Theta'/Theta_ref)), C_s = gamma p/Theta,
+//    P0_s = p'_s - C_s Theta'.
+//  short step (length dtau), from state n to n+1
+//    p' = P0_s + C_s Theta';  U+ = U + dtau (S_U - dx p'),  V+ likewise;
+//    rho~ = rho' - dtau (dx U+ + dy V+);
+//    Theta~ = Theta' + dtau (R_Theta - dx(theta_x U+) - dy(theta_y V+));
+//    vertically, with X* = beta X+ + (1-beta) X and thf = theta_s on faces:
+//    rho'+ = rho~ - dtau dz(W*),  Theta'+ = Theta~ - dtau dz(thf W*),
+//    W+ = W + dtau (S_W - dz p* - g rho* on faces), which is tridiagonal in W+.
+#include "hevi_kernels.h"
+
+#include <cstdint>
+
+namespace hv {
+namespace {
+
+constexpr int SEG = 16;            // lanes per column
+constexpr int BLOCK = 256;         // threads per block
+constexpr int CPB = BLOCK / SEG;   // columns per block
+
+constexpr double kGamma = 1.4;
+constexpr double kGrav = 9.80665;
+
+template <typename T, int L>
+using vec_t = T __attribute__((ext_vector_type(L)));
+
+__device__ __forceinline__ int wrapc(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// Storage orders of a 3D field with nz levels per column.
+struct KIJ {
+    static constexpr bool kContig = true;
+    __device__ static size_t at(int i, int j, int k, int nx, int ny, int nz)
+    {
+        return ((size_t)j * nx + i) * nz + k;
+    }
+};
+struct IJK {
+    static constexpr bool kContig = false;
+    __device__ static size_t at(int i, int j, int k, int nx, int ny, int nz)
+    {
+        return ((size_t)k * ny + j) * nx + i;
+    }
+};
+
+template <class Lay, int L>
+struct Lane {
+    int i, j, p, k0, nx, ny, nz;
+    size_t kstride;
+
+    __device__ Lane(const Geom &g, int col)
+    {
+        nx = g.nx; ny = g.ny; nz = g.nz;
+        i = col % nx;
+        j = col / nx;
+        p = threadIdx.x % SEG;
+        k0 = p * L;
+        kstride = Lay::kContig ? 1 : (size_t)nx * ny;
+    }
+    __device__ size_t off(int di, int dj) const
+    {
+        return Lay::at(wrapc(i + di, nx), wrapc(j + dj, ny), k0, nx, ny, nz);
+    }
+    template <typename T>
+    __device__ void load(const T *__restrict__ a, int di, int dj, T (&x)[L]) const
+    {
+        const T *q = a + off(di, dj);
+        if constexpr (Lay::kContig) {
+            const vec_t<T, L> t = *reinterpret_cast<const vec_t<T, L> *>(q);
+#pragma unroll
+            for (int l = 0; l < L; ++l) x[l] = t[l];
+        } else {
+#pragma unroll
+            for (int l = 0; l < L; ++l) x[l] = q[(size_t)l * kstride];
+        }
+    }
+    template <typename T, typename S>
+    __device__ void store(T *__restrict__ a, const S (&x)[L]) const
+    {
+        T *q = a + off(0, 0);
+        if constexpr (Lay::kContig) {
+            vec_t<T, L> t;
+#pragma unroll
+            for (int l = 0; l < L; ++l) t[l] = (T)x[l];
+            *reinterpret_cast<vec_t<T, L> *>(q) = t;
+        } else {
+#pragma unroll
+            for (int l = 0; l < L; ++l) q[(size_t)l * kstride] = (T)x[l];
+        }
+    }
+    // per-level constant of the lane's levels (+ offset), as type S
+    template <typename S>
+    __device__ void vmet(const double *__restrict__ vm, int f, S (&x)[L], int koff = 0) const
+    {
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            int k = k0 + l + koff;
+            k = k < 0 ? 0 : (k >= nz ? nz - 1 : k);
+            x[l] = (S)vm[(size_t)f * nz + k];
+        }
+    }
+};
+
+// value of lane p-1 (lane 0 keeps its own) / of lane p+1 (lane 15 keeps its own)
+template <typename T> __device__ __forceinline__ T from_below(T x) { return __shfl_up(x, 1u, SEG); }
+template <typename T> __device__ __forceinline__ T from_above(T x) { return __shfl_down(x, 1u, SEG); }
+
+// e[0..L+3] = levels k0-2 .. k0+L+1 of a per-lane array x.  Below the column
+// the bottom value is repeated (zero-gradient ghost); above it, either the top
+// value is repeated (cell quantities) or zero is used (level-face quantities,
+// whose face nz is the rigid lid).
+template <typename T, int L>
+__device__ __forceinline__ void extend2(const T (&x)[L], T (&e)[L + 4], int p, bool zero_top)
+{
+    const T b2 = from_below(x[L - 2]);
+    const T b1 = from_below(x[L - 1]);
+    const T a0 = from_above(x[0]);
+    const T a1 = from_above(x[1]);
+    const bool bot = (p == 0), top = (p == SEG - 1);
+    e[0] = bot ? x[0] : b2;
+    e[1] = bot ? x[0] : b1;
+#pragma unroll
+    for (int l = 0; l < L; ++l) e[2 + l] = x[l];
+    const T topv = zero_top ? T(0) : x[L - 1];
+    e[L + 2] = top ? topv : a0;
+    e[L + 3] = top ? topv : a1;
+}
+
+template <typename T> __device__ __forceinline__ T xexpm1(T x) { return expm1(x); }
+template <> __device__ __forceinline__ float xexpm1<float>(float x) { return expm1f(x); }
+template <typename T> __device__ __forceinline__ T xlog1p(T x) { return log1p(x); }
+template <> __device__ __forceinline__ float xlog1p<float>(float x) { return log1pf(x); }
+
+// Koren increment psi(D+/D-) * D- without the division:
+// psi(r) = max(0, min(2r, (1 + 2r)/3, 2))  (Koren 1993, kappa = 1/3).
+template <typename T>
+__device__ __forceinline__ T koren_phi(T dm, T dp)
+{
+    const T t = (dm + T(2) * dp) * T(1.0 / 3.0);
+    const T pos = fmax(T(0), fmin(fmin(T(2) * dp, t), T(2) * dm));
+    const T neg = fmin(T(0), fmax(fmax(T(2) * dp, t), T(2) * dm));
+    return dm > T(0) ? pos : (dm < T(0) ? neg : T(0));
+}
+
+// Limited face value between L and R for mass flux m (m >= 0: from L).
+template <typename T>
+__device__ __forceinline__ T kface(T qLL, T qL, T qR, T qRR, T m)
+{
+    const bool up = m >= T(0);
+    const T q0 = up ? qLL : qRR;
+    const T q1 = up ? qL : qR;
+    const T q2 = up ? qR : qL;
+    return q1 + T(0.5) * koren_phi(q1 - q0, q2 - q1);
+}
+
+// --------------------------------------------------------------------------
+// slow sweep, part 1: specific velocities, theta and stage coefficients
+// --------------------------------------------------------------------------
+template <typename T, class Lay, int L>
+__global__ __launch_bounds__(BLOCK) void k_slow_prep(
+    Geom g, const double *__restrict__ vm, const T *__restrict__ rp, const T *__restrict__ U,
+    const T *__restrict__ V, const T *__restrict__ W, const T *__restrict__ tp,
+    T *__restrict__ uo, T *__restrict__ vo, T *__restrict__ wo, T *__restrict__ tho,
+    T *__restrict__ P0o, T *__restrict__ Cso)
+{
+    const int col = blockIdx.x * CPB + threadIdx.x / SEG;
+    if (col >= g.nx * g.ny) return;
+    const Lane<Lay, L> ln(g, col);
+
+    T r0[L], rw[L], rs[L], Uc[L], Vc[L], Wc[L], tc[L];
+    ln.load(rp, 0, 0, r0);
+    ln.load(rp, -1, 0, rw);
+    ln.load(rp, 0, -1, rs);
+    ln.load(U, 0, 0, Uc);
+    ln.load(V, 0, 0, Vc);
+    ln.load(W, 0, 0, Wc);
+    ln.load(tp, 0, 0, tc);
+    T rref[L], rtref[L], pref[L], a[L], b[L];
+    ln.vmet(vm, VM_RHO, rref);
+    ln.vmet(vm, VM_RT, rtref);
+    ln.vmet(vm, VM_P, pref);
+    ln.vmet(vm, VM_A, a);
+    ln.vmet(vm, VM_B, b);
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        r0[l] = rref[l] + r0[l];
+        rw[l] = rref[l] + rw[l];
+        rs[l] = rref[l] + rs[l];
+    }
+    const T rbelow = from_below(r0[L - 1]);
+    T u[L], v[L], w[L], th[L], P0[L], Cs[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        const int k = ln.k0 + l;
+        u[l] = Uc[l] / (T(0.5) * (rw[l] + r0[l]));
+        v[l] = Vc[l] / (T(0.5) * (rs[l] + r0[l]));
+        const T rb = (l == 0) ? rbelow : r0[l - 1];
+        w[l] = (k == 0) ? T(0) : Wc[l] / (a[l] * r0[l] + b[l] * rb);
+        th[l] = (rtref[l] + tc[l]) / r0[l];
+        const T pps = pref[l] * xexpm1(T(kGamma) * xlog1p(tc[l] / rtref[l]));
+        const T cs = T(kGamma) * (pref[l] + pps) / (rtref[l] + tc[l]);
+        Cs[l] = cs;
+        P0[l] = pps - cs * tc[l];
+    }
+    ln.store(uo, u);
+    ln.store(vo, v);
+    ln.store(wo, w);
+    ln.store(tho, th);
+    ln.store(P0o, P0);
+    ln.store(Cso, Cs);
+}
+
+// --------------------------------------------------------------------------
+// slow sweep, part 2: advective tendencies S_U, S_V, S_W and R_Theta
+// --------------------------------------------------------------------------
+template <typename T, class Lay, int L>
+__device__ __forceinline__ void slow_su(const Lane<Lay, L> &ln, T rdx, T rdy, const T (&rdz)[L],
+                                        const T *__restrict__ U, const T *__restrict__ V,
+                                        const T *__restrict__ W, const T *__restrict__ uu,
+                                        T *__restrict__ SU)
+{
+    T ux[5][L], uy[4][L];
+#pragma unroll
+    for (int d = 0; d < 5; ++d) ln.load(uu, d - 2, 0, ux[d]);
+    ln.load(uu, 0, -2, uy[0]);
+    ln.load(uu, 0, -1, uy[1]);
+    ln.load(uu, 0, 1, uy[2]);
+    ln.load(uu, 0, 2, uy[3]);
+    T Um[L], U0[L], Up[L], Vw0[L], V00[L], Vw1[L], V01[L], Wm[L], W0[L];
+    ln.load(U, -1, 0, Um);
+    ln.load(U, 0, 0, U0);
+    ln.load(U, 1, 0, Up);
+    ln.load(V, -1, 0, Vw0);
+    ln.load(V, 0, 0, V00);
+    ln.load(V, -1, 1, Vw1);
+    ln.load(V, 0, 1, V01);
+    ln.load(W, -1, 0, Wm);
+    ln.load(W, 0, 0, W0);
+    T ue[L + 4];
+    extend2(ux[2], ue, ln.p, false);
+    const bool top = (ln.p == SEG - 1);
+    const T Wm_a = from_above(Wm[0]), W0_a = from_above(W0[0]);
+    const T Wm_up = top ? T(0) : Wm_a;
+    const T W0_up = top ? T(0) : W0_a;
+    T fz[L + 1];
+#pragma unroll
+    for (int l = 0; l <= L; ++l) {
+        const int kf = ln.k0 + l;
+        const T wa = (l < L) ? Wm[l] : Wm_up;
+        const T wb = (l < L) ? W0[l] : W0_up;
+        const T m = T(0.5) * (wa + wb);
+        const T q = kface(ue[l], ue[l + 1], ue[l + 2], ue[l + 3], m);
+        fz[l] = (kf == 0 || kf == ln.nz) ? T(0) : m * q;
+    }
+    T out[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        const T m0 = T(0.5) * (Um[l] + U0[l]);
+        const T fx0 = m0 * kface(ux[0][l], ux[1][l], ux[2][l], ux[3][l], m0);
+        const T m1 = T(0.5) * (U0[l] + Up[l]);
+        const T fx1 = m1 * kface(ux[1][l], ux[2][l], ux[3][l], ux[4][l], m1);
+        const T n0 = T(0.5) * (Vw0[l] + V00[l]);
+        const T fy0 = n0 * kface(uy[0][l], uy[1][l], ux[2][l], uy[2][l], n0);
+        const T n1 = T(0.5) * (Vw1[l] + V01[l]);
+        const T fy1 = n1 * kface(uy[1][l], ux[2][l], uy[2][l], uy[3][l], n1);
+        out[l] = -((fx1 - fx0) * rdx + (fy1 - fy0) * rdy + (fz[l + 1] - fz[l]) * rdz[l]);
+    }
+    ln.store(SU, out);
+}
+
+template <typename T, class Lay, int L>
+__device__ __forceinline__ void slow_sv(const Lane<Lay, L> &ln, T rdx, T rdy, const T (&rdz)[L],
+                                        const T *__restrict__ U, const T *__restrict__ V,
+                                        const T *__restrict__ W, const T *__restrict__ vv,
+                                        T *__restrict__ SV)
+{
+    T vy[5][L], vx[4][L];
+#pragma unroll
+    for (int d = 0; d < 5; ++d) ln.load(vv, 0, d - 2, vy[d]);
+    ln.load(vv, -2, 0, vx[0]);
+    ln.load(vv, -1, 0, vx[1]);
+    ln.load(vv, 1, 0, vx[2]);
+    ln.load(vv, 2, 0, vx[3]);
+    T Vm[L], V0[L], Vp[L], Us0[L], U00[L], Us1[L], U10[L], Wm[L], W0[L];
+    ln.load(V, 0, -1, Vm);
+    ln.load(V, 0, 0, V0);
+    ln.load(V, 0, 1, Vp);
+    ln.load(U, 0, -1, Us0);
+    ln.load(U, 0, 0, U00);
+    ln.load(U, 1, -1, Us1);
+    ln.load(U, 1, 0, U10);
+    ln.load(W, 0, -1, Wm);
+    ln.load(W, 0, 0, W0);
+    T ve[L + 4];
+    extend2(vy[2], ve, ln.p, false);
+    const bool top = (ln.p == SEG - 1);
+    const T Wm_a = from_above(Wm[0]), W0_a = from_above(W0[0]);
+    const T Wm_up = top ? T(0) : Wm_a;
+    const T W0_up = top ? T(0) : W0_a;
+    T fz[L + 1];
+#pragma unroll
+    for (int l = 0; l <= L; ++l) {
+        const int kf = ln.k0 + l;
+        const T wa = (l < L) ? Wm[l] : Wm_up;
+        const T wb = (l < L) ? W0[l] : W0_up;
+        const T m = T(0.5) * (wa + wb);
+        const T q = kface(ve[l], ve[l + 1], ve[l + 2], ve[l + 3], m);
+        fz[l] = (kf == 0 || kf == ln.nz) ? T(0) : m * q;
+    }
+    T out[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        const T m0 = T(0.5) * (Us0[l] + U00[l]);
+        const T fx0 = m0 * kface(vx[0][l], vx[1][l], vy[2][l], vx[2][l], m0);
+        const T m1 = T(0.5) * (Us1[l] + U10[l]);
+        const T fx1 = m1 * kface(vx[1][l], vy[2][l], vx[2][l], vx[3][l], m1);
+        const T n0 = T(0.5) * (Vm[l] + V0[l]);
+        const T fy0 = n0 * kface(vy[0][l], vy[1][l], vy[2][l], vy[3][l], n0);
+        const T n1 = T(0.5) * (V0[l] + Vp[l]);
+        const T fy1 = n1 * kface(vy[1][l], vy[2][l], vy[3][l], vy[4][l], n1);
+        out[l] = -((fx1 - fx0) * rdx + (fy1 - fy0) * rdy + (fz[l + 1] - fz[l]) * rdz[l]);
+    }
+    ln.store(SV, out);
+}
+
+template <typename T, class Lay, int L>
+__device__ __forceinline__ void slow_sw(const Lane<Lay, L> &ln, T rdx, T rdy,
+                                        const double *__restrict__ vm, const T *__restrict__ U,
+                                        const T *__restrict__ V, const T *__restrict__ W,
+                                        const T *__restrict__ ww, T *__restrict__ SW)
+{
+    T wx[5][L], wy[4][L];
+#pragma unroll
+    for (int d = 0; d < 5; ++d) ln.load(ww, d - 2, 0, wx[d]);
+    ln.load(ww, 0, -2, wy[0]);
+    ln.load(ww, 0, -1, wy[1]);
+    ln.load(ww, 0, 1, wy[2]);
+    ln.load(ww, 0, 2, wy[3]);
+    T U0[L], U1[L], V0[L], V1[L], W0[L];
+    ln.load(U, 0, 0, U0);
+    ln.load(U, 1, 0, U1);
+    ln.load(V, 0, 0, V0);
+    ln.load(V, 0, 1, V1);
+    ln.load(W, 0, 0, W0);
+    // level below the lane's first level (unused on the bottom level face)
+    const T U0b = from_below(U0[L - 1]), U1b = from_below(U1[L - 1]);
+    const T V0b = from_below(V0[L - 1]), V1b = from_below(V1[L - 1]);
+    T we[L + 4], We[L + 4];
+    extend2(wx[2], we, ln.p, true);
+    extend2(W0, We, ln.p, true);
+    T rdzf[L];
+    ln.vmet(vm, VM_RDZF, rdzf);
+    // vertical fluxes at the cell centres cc = k0-1 .. k0+L-1
+    T fz[L + 1];
+#pragma unroll
+    for (int l = 0; l <= L; ++l) {
+        const T m = T(0.5) * (We[l + 1] + We[l + 2]);
+        fz[l] = m * kface(we[l], we[l + 1], we[l + 2], we[l + 3], m);
+    }
+    T out[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        const int k = ln.k0 + l;
+        const T u0b = (l == 0) ? U0b : U0[l - 1];
+        const T u1b = (l == 0) ? U1b : U1[l - 1];
+        const T v0b = (l == 0) ? V0b : V0[l - 1];
+        const T v1b = (l == 0) ? V1b : V1[l - 1];
+        const T m0 = T(0.5) * (u0b + U0[l]);
+        const T fx0 = m0 * kface(wx[0][l], wx[1][l], wx[2][l], wx[3][l], m0);
+        const T m1 = T(0.5) * (u1b + U1[l]);
+        const T fx1 = m1 * kface(wx[1][l], wx[2][l], wx[3][l], wx[4][l], m1);
+        const T n0 = T(0.5) * (v0b + V0[l]);
+        const T fy0 = n0 * kface(wy[0][l], wy[1][l], wx[2][l], wy[2][l], n0);
+        const T n1 = T(0.5) * (v1b + V1[l]);
+        const T fy1 = n1 * kface(wy[1][l], wx[2][l], wy[2][l], wy[3][l], n1);
+        const T s = -((fx1 - fx0) * rdx + (fy1 - fy0) * rdy + (fz[l + 1] - fz[l]) * rdzf[l]);
+        out[l] = (k == 0) ? T(0) : s;
+    }
+    ln.store(SW, out);
+}
+
+template <typename T, class Lay, int L>
+__device__ __forceinline__ void slow_rt(const Lane<Lay, L> &ln, T rdx, T rdy, const T (&rdz)[L],
+                                        const double *__restrict__ vm, const T *__restrict__ U,
+                                        const T *__restrict__ V, const T *__restrict__ W,
+                                        const T *__restrict__ th, T *__restrict__ RT)
+{
+    T tx[5][L], ty[4][L];
+#pragma unroll
+    for (int d = 0; d < 5; ++d) ln.load(th, d - 2, 0, tx[d]);
+    ln.load(th, 0, -2, ty[0]);
+    ln.load(th, 0, -1, ty[1]);
+    ln.load(th, 0, 1, ty[2]);
+    ln.load(th, 0, 2, ty[3]);
+    T U0[L], U1[L], V0[L], V1[L], W0[L];
+    ln.load(U, 0, 0, U0);
+    ln.load(U, 1, 0, U1);
+    ln.load(V, 0, 0, V0);
+    ln.load(V, 0, 1, V1);
+    ln.load(W, 0, 0, W0);
+    T te[L + 4];
+    extend2(tx[2], te, ln.p, false);
+    const bool top = (ln.p == SEG - 1);
+    const T W_a = from_above(W0[0]);
+    const T W_up = top ? T(0) : W_a;
+    T a[L + 1], b[L + 1];
+#pragma unroll
+    for (int l = 0; l <= L; ++l) {
+        int k = ln.k0 + l;
+        k = k >= ln.nz ? ln.nz - 1 : k;
+        a[l] = (T)vm[(size_t)VM_A * ln.nz + k];
+        b[l] = (T)vm[(size_t)VM_B * ln.nz + k];
+    }
+    T gz[L + 1];
+#pragma unroll
+    for (int l = 0; l <= L; ++l) {
+        const int kf = ln.k0 + l;
+        const T m = (l < L) ? W0[l] : W_up;
+        const T tl = kface(te[l], te[l + 1], te[l + 2], te[l + 3], m);
+        const T tcen = a[l] * te[l + 2] + b[l] * te[l + 1];
+        gz[l] = (kf == 0 || kf == ln.nz) ? T(0) : m * (tl - tcen);
+    }
+    T out[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        const T m0 = U0[l];
+        const T g0 = m0 * (kface(tx[0][l], tx[1][l], tx[2][l], tx[3][l], m0) -
+                           T(0.5) * (tx[1][l] + tx[2][l]));
+        const T m1 = U1[l];
+        const T g1 = m1 * (kface(tx[1][l], tx[2][l], tx[3][l], tx[4][l], m1) -
+                           T(0.5) * (tx[2][l] + tx[3][l]));
+        const T n0 = V0[l];
+        const T h0 = n0 * (kface(ty[0][l], ty[1][l], tx[2][l], ty[2][l], n0) -
+                           T(0.5) * (ty[1][l] + tx[2][l]));
+        const T n1 = V1[l];
+        const T h1 = n1 * (kface(ty[1][l], tx[2][l], ty[2][l], ty[3][l], n1) -
+                           T(0.5) * (tx[2][l] + ty[2][l]));
+        out[l] = -((g1 - g0) * rdx + (h1 - h0) * rdy + (gz[l + 1] - gz[l]) * rdz[l]);
+    }
+    ln.store(RT, out);
+}
+
+template <typename T, class Lay, int L>
+__global__ __launch_bounds__(BLOCK) void k_slow_flux(
+    Geom g, const double *__restrict__ vm, const T *__restrict__ U, const T *__restrict__ V,
+    const T *__restrict__ W, const T *__restrict__ uu, const T *__restrict__ vv,
+    const T *__restrict__ ww, const T *__restrict__ th, T *__restrict__ SU, T *__restrict__ SV,
+    T *__restrict__ SW, T *__restrict__ RT)
+{
+    const int col = blockIdx.x * CPB + threadIdx.x / SEG;
+    if (col >= g.nx * g.ny) return;
+    const Lane<Lay, L> ln(g, col);
+    const T rdx = (T)g.rdx, rdy = (T)g.rdy;
+    T rdz[L];
+    ln.vmet(vm, VM_RDZ, rdz);
+    slow_su(ln, rdx, rdy, rdz, U, V, W, uu, SU);
+    slow_sv(ln, rdx, rdy, rdz, U, V, W, vv, SV);
+    slow_sw(ln, rdx, rdy, vm, U, V, W, ww, SW);
+    slow_rt(ln, rdx, rdy, rdz, vm, U, V, W, th, RT);
+}
+
+// --------------------------------------------------------------------------
+// short step: horizontally explicit part, then the column solve
+// --------------------------------------------------------------------------
+
+// Solve the segment's tridiagonal system A x_{r-1} + B x_r + C x_{r+1} = D,
+// one row per level face, lane p holding rows p*L .. p*L+L-1.  A of the
+// first row and C of the last row of the column must be 0.
+template <typename S, int L>
+__device__ __forceinline__ void segment_solve(int p, const S (&A)[L], const S (&B)[L],
+                                              const S (&C)[L], const S (&D)[L], S (&x)[L])
+{
+    // interior rows 0..L-2 in terms of X_{p-1} (last unknown of the lane
+    // below) and X_p (this lane's last unknown): x_l = xg + xa X_{p-1} + xb X_p
+    constexpr int n = L - 1;
+    S gp[L], yg[L], ya[L], yb[L];
+#pragma unroll
+    for (int l = 0; l < n; ++l) {
+        const S den = (l == 0) ? B[0] : B[l] - A[l] * gp[l - 1];
+        const S rden = S(1) / den;
+        gp[l] = (l < n - 1) ? C[l] * rden : S(0);
+        const S rg = D[l], ra = (l == 0) ? -A[0] : S(0), rb = (l == n - 1) ? -C[l] : S(0);
+        if (l == 0) {
+            yg[0] = rg * rden;
+            ya[0] = ra * rden;
+            yb[0] = rb * rden;
+        } else {
+            yg[l] = (rg - A[l] * yg[l - 1]) * rden;
+            ya[l] = (ra - A[l] * ya[l - 1]) * rden;
+            yb[l] = (rb - A[l] * yb[l - 1]) * rden;
+        }
+    }
+#pragma unroll
+    for (int l = n - 2; l >= 0; --l) {
+        yg[l] = yg[l] - gp[l] * yg[l + 1];
+        ya[l] = ya[l] - gp[l] * ya[l + 1];
+        yb[l] = yb[l] - gp[l] * yb[l + 1];
+    }
+    // reduced equation of the lane's last row, in X_{p-1}, X_p, X_{p+1}
+    const S ga = from_above(ya[0]), gb = from_above(yb[0]), gg = from_above(yg[0]);
+    const S Ab = A[L - 1] * ya[n - 1];
+    const S Bb = B[L - 1] + A[L - 1] * yb[n - 1] + C[L - 1] * ga;
+    const S Cb = C[L - 1] * gb;
+    const S Db = D[L - 1] - A[L - 1] * yg[n - 1] - C[L - 1] * gg;
+    const S rB = S(1) / Bb;
+    S a = Ab * rB, c = Cb * rB, d = Db * rB;
+    // parallel cyclic reduction over the 16 interface rows
+#pragma unroll
+    for (int s = 1; s < SEG; s <<= 1) {
+        const bool hasm = p >= s, hasp = p + s < SEG;
+        const S am = __shfl_up(a, (unsigned)s, SEG), cm = __shfl_up(c, (unsigned)s, SEG);
+        const S dm = __shfl_up(d, (unsigned)s, SEG);
+        const S ap = __shfl_down(a, (unsigned)s, SEG), cp = __shfl_down(c, (unsigned)s, SEG);
+        const S dp = __shfl_down(d, (unsigned)s, SEG);
+        const S amv = hasm ? am : S(0), cmv = hasm ? cm : S(0), dmv = hasm ? dm : S(0);
+        const S apv = hasp ? ap : S(0), cpv = hasp ? cp : S(0), dpv = hasp ? dp : S(0);
+        const S rb2 = S(1) / (S(1) - a * cmv - c * apv);
+        const S dn = (d - a * dmv - c * dpv) * rb2;
+        const S an = -a * amv * rb2;
+        const S cn = -c * cpv * rb2;
+        a = an;
+        c = cn;
+        d = dn;
+    }
+    const S X = d;
+    const S Xs = from_below(X);
+    const S Xb = (p == 0) ? S(0) : Xs;
+#pragma unroll
+    for (int l = 0; l < n; ++l) x[l] = yg[l] + ya[l] * Xb + yb[l] * X;
+    x[L - 1] = X;
+}
+
+template <typename T, typename S, class Lay, int L>
+__global__ __launch_bounds__(BLOCK) void k_short_step(
+    Geom g, const double *__restrict__ vm, double dtau_d, const T *__restrict__ rp,
+    const T *__restrict__ U, const T *__restrict__ V, const T *__restrict__ W,
+    const T *__restrict__ tp, T *__restrict__ rpo, T *__restrict__ Uo, T *__restrict__ Vo,
+    T *__restrict__ Wo, T *__restrict__ tpo, const T *__restrict__ SU,
+    const T *__restrict__ SV, const T *__restrict__ SW, const T *__restrict__ RT,
+    const T *__restrict__ ths, const T *__restrict__ P0, const T *__restrict__ Cs)
+{
+    const int col = blockIdx.x * CPB + threadIdx.x / SEG;
+    if (col >= g.nx * g.ny) return;
+    const Lane<Lay, L> ln(g, col);
+    const T dt = (T)dtau_d, rdx = (T)g.rdx, rdy = (T)g.rdy;
+
+    // ---- horizontally explicit part (storage precision) ----
+    T pc[L], pw[L], pe[L], ps[L], pn[L];
+    T P0c[L], Csc[L], tpc[L];
+    {
+        T a[L], c[L], t[L];
+        ln.load(P0, 0, 0, P0c);
+        ln.load(Cs, 0, 0, Csc);
+        ln.load(tp, 0, 0, tpc);
+#pragma unroll
+        for (int l = 0; l < L; ++l) pc[l] = P0c[l] + Csc[l] * tpc[l];
+        ln.load(P0, -1, 0, a); ln.load(Cs, -1, 0, c); ln.load(tp, -1, 0, t);
+#pragma unroll
+        for (int l = 0; l < L; ++l) pw[l] = a[l] + c[l] * t[l];
+        ln.load(P0, 1, 0, a); ln.load(Cs, 1, 0, c); ln.load(tp, 1, 0, t);
+#pragma unroll
+        for (int l = 0; l < L; ++l) pe[l] = a[l] + c[l] * t[l];
+        ln.load(P0, 0, -1, a); ln.load(Cs, 0, -1, c); ln.load(tp, 0, -1, t);
+#pragma unroll
+        for (int l = 0; l < L; ++l) ps[l] = a[l] + c[l] * t[l];
+        ln.load(P0, 0, 1, a); ln.load(Cs, 0, 1, c); ln.load(tp, 0, 1, t);
+#pragma unroll
+        for (int l = 0; l < L; ++l) pn[l] = a[l] + c[l] * t[l];
+    }
+    T thc[L], thw[L], the[L], tsth[L], tnth[L];
+    ln.load(ths, 0, 0, thc);
+    ln.load(ths, -1, 0, thw);
+    ln.load(ths, 1, 0, the);
+    ln.load(ths, 0, -1, tsth);
+    ln.load(ths, 0, 1, tnth);
+    T U0[L], U1[L], SU0[L], SU1[L], V0[L], V1[L], SV0[L], SV1[L];
+    ln.load(U, 0, 0, U0);
+    ln.load(U, 1, 0, U1);
+    ln.load(SU, 0, 0, SU0);
+    ln.load(SU, 1, 0, SU1);
+    ln.load(V, 0, 0, V0);
+    ln.load(V, 0, 1, V1);
+    ln.load(SV, 0, 0, SV0);
+    ln.load(SV, 0, 1, SV1);
+    T rpc[L], Wc[L], SWc[L], RTc[L];
+    ln.load(rp, 0, 0, rpc);
+    ln.load(W, 0, 0, Wc);
+    ln.load(SW, 0, 0, SWc);
+    ln.load(RT, 0, 0, RTc);
+
+    T Up[L], Vp[L], rt[L], tt[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        const T up0 = U0[l] + dt * (SU0[l] - (pc[l] - pw[l]) * rdx);
+        const T up1 = U1[l] + dt * (SU1[l] - (pe[l] - pc[l]) * rdx);
+        const T vp0 = V0[l] + dt * (SV0[l] - (pc[l] - ps[l]) * rdy);
+        const T vp1 = V1[l] + dt * (SV1[l] - (pn[l] - pc[l]) * rdy);
+        const T div = (up1 - up0) * rdx + (vp1 - vp0) * rdy;
+        const T fw = T(0.5) * (thw[l] + thc[l]), fe = T(0.5) * (thc[l] + the[l]);
+        const T fs = T(0.5) * (tsth[l] + thc[l]), fn = T(0.5) * (thc[l] + tnth[l]);
+        const T tdiv = (fe * up1 - fw * up0) * rdx + (fn * vp1 - fs * vp0) * rdy;
+        Up[l] = up0;
+        Vp[l] = vp0;
+        rt[l] = rpc[l] - dt * div;
+        tt[l] = tpc[l] + dt * (RTc[l] - tdiv);
+    }
+    ln.store(Uo, Up);
+    ln.store(Vo, Vp);
+
+    // ---- vertically implicit part (solve precision S) ----
+    const S be = (S)g.beta, dts = (S)dtau_d;
+    const S one_m_be = S(1) - be;
+    const S mu = be * be * dts * dts;
+    const S grav = (S)kGrav;
+    const int p = ln.p;
+    const bool bot = (p == 0), top = (p == SEG - 1);
+    S rdz[L], rdzf[L], av[L], bv[L];
+    ln.vmet(vm, VM_RDZ, rdz);
+    ln.vmet(vm, VM_RDZF, rdzf);
+    ln.vmet(vm, VM_A, av);
+    ln.vmet(vm, VM_B, bv);
+    const S rdz_b = from_below(rdz[L - 1]);   // 1/dz of the level below the lane
+
+    // theta_s on the lane's level faces k0..k0+L-1, and on face k0+L
+    const T th_b = from_below(thc[L - 1]);
+    S thf[L + 1];
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        const S tb = (S)((l == 0) ? th_b : thc[l - 1]);
+        thf[l] = (ln.k0 + l == 0) ? S(0) : av[l] * (S)thc[l] + bv[l] * tb;
+    }
+    {
+        const S t = from_above(thf[0]);
+        thf[L] = top ? S(0) : t;
+    }
+    const T w_up = from_above(Wc[0]);
+    S Wf[L + 1];
+#pragma unroll
+    for (int l = 0; l < L; ++l) Wf[l] = (S)Wc[l];
+    Wf[L] = top ? S(0) : (S)w_up;
+
+    // the state each cell reaches with W+ = 0
+    S thE[L], rhE[L], pE[L], rEs[L], Cc[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        const S f = one_m_be * dts * rdz[l];
+        thE[l] = (S)tt[l] - f * (thf[l + 1] * Wf[l + 1] - thf[l] * Wf[l]);
+        rhE[l] = (S)rt[l] - f * (Wf[l + 1] - Wf[l]);
+        Cc[l] = (S)Csc[l];
+        pE[l] = be * ((S)P0c[l] + Cc[l] * thE[l]) + one_m_be * (S)pc[l];
+        rEs[l] = be * rhE[l] + one_m_be * (S)rpc[l];
+    }
+    const S C_b = from_below(Cc[L - 1]), thf_b = from_below(thf[L - 1]);
+    const S pE_b = from_below(pE[L - 1]), rEs_b = from_below(rEs[L - 1]);
+
+    S A[L], B[L], C[L], D[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        const int k = ln.k0 + l;
+        const S Cm = (l == 0) ? C_b : Cc[l - 1];
+        const S tfm = (l == 0) ? thf_b : thf[l - 1];
+        const S pEm = (l == 0) ? pE_b : pE[l - 1];
+        const S rEm = (l == 0) ? rEs_b : rEs[l - 1];
+        const S rdzm = (l == 0) ? rdz_b : rdz[l - 1];
+        const S rdzp = rdz[l];
+        const S fA = -mu * Cm * tfm * (rdzf[l] * rdzm) + mu * grav * bv[l] * rdzm;
+        const S fC = -mu * Cc[l] * thf[l + 1] * (rdzf[l] * rdzp) - mu * grav * av[l] * rdzp;
+        const S fB = S(1) + mu * thf[l] * (Cc[l] * rdzp + Cm * rdzm) * rdzf[l] +
+                     mu * grav * (av[l] * rdzp - bv[l] * rdzm);
+        const S fD = Wf[l] + dts * (S)SWc[l] - (dts * rdzf[l]) * (pE[l] - pEm) -
+                     dts * grav * (av[l] * rEs[l] + bv[l] * rEm);
+        const bool lid = (k == 0);
+        A[l] = lid ? S(0) : fA;
+        B[l] = lid ? S(1) : fB;
+        C[l] = (lid || k == ln.nz - 1) ? S(0) : fC;
+        D[l] = lid ? S(0) : fD;
+    }
+    S x[L];
+    segment_solve<S, L>(p, A, B, C, D, x);
+
+    const S x_up = from_above(x[0]);
+    const S xt = top ? S(0) : x_up;
+    S rpn[L], tpn[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        const S xu = (l < L - 1) ? x[l + 1] : xt;
+        const S f = be * dts * rdz[l];
+        rpn[l] = rhE[l] - f * (xu - x[l]);
+        tpn[l] = thE[l] - f * (thf[l + 1] * xu - thf[l] * x[l]);
+    }
+    (void)bot;
+    ln.store(Wo, x);
+    ln.store(rpo, rpn);
+    ln.store(tpo, tpn);
+}
+
+// --------------------------------------------------------------------------
+// float64 sums with a fixed two-level order
+// --------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum(double v, double *sh)
+{
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+#pragma unroll
+    for (int s = BLOCK / 2; s > 0; s >>= 1) {
+        if (t < s) sh[t] = sh[t] + sh[t + s];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+template <typename T, class Lay, int L>
+__global__ __launch_bounds__(BLOCK) void k_mass_partial(Geom g, const double *__restrict__ vm,
+                                                        const T *__restrict__ rp,
+                                                        double *__restrict__ part)
+{
+    __shared__ double sh[BLOCK];
+    const int col = blockIdx.x * CPB + threadIdx.x / SEG;
+    double acc = 0.0;
+    if (col < g.nx * g.ny) {
+        const Lane<Lay, L> ln(g, col);
+        T r[L];
+        double vol[L];
+        ln.load(rp, 0, 0, r);
+        ln.vmet(vm, VM_VOL, vol);
+#pragma unroll
+        for (int l = 0; l < L; ++l) acc += (double)r[l] * vol[l];
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+template <typename T, class Lay, int L>
+__global__ __launch_bounds__(BLOCK) void k_energy_partial(
+    Geom g, const double *__restrict__ vm, const T *__restrict__ rp, const T *__restrict__ U,
+    const T *__restrict__ V, const T *__restrict__ W, const T *__restrict__ tp,
+    double *__restrict__ part)
+{
+    __shared__ double sh[BLOCK];
+    const int col = blockIdx.x * CPB + threadIdx.x / SEG;
+    double acc = 0.0;
+    if (col < g.nx * g.ny) {
+        const Lane<Lay, L> ln(g, col);
+        T r[L], u0[L], u1[L], v0[L], v1[L], w0[L], t[L];
+        ln.load(rp, 0, 0, r);
+        ln.load(U, 0, 0, u0);
+        ln.load(U, 1, 0, u1);
+        ln.load(V, 0, 0, v0);
+        ln.load(V, 0, 1, v1);
+        ln.load(W, 0, 0, w0);
+        ln.load(tp, 0, 0, t);
+        const T wt = from_above(w0[0]);
+        double vol[L], rref[L], rtref[L], pref[L], zc[L];
+        ln.vmet(vm, VM_VOL, vol);
+        ln.vmet(vm, VM_RHO, rref);
+        ln.vmet(vm, VM_RT, rtref);
+        ln.vmet(vm, VM_P, pref);
+        ln.vmet(vm, VM_ZC, zc);
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            const double rho = rref[l] + (double)r[l];
+            const double wu = (l < L - 1) ? (double)w0[l + 1] : (ln.p == SEG - 1 ? 0.0 : (double)wt);
+            const double a = (double)u0[l], b = (double)u1[l], c = (double)v0[l], d = (double)v1[l];
+            const double e = (double)w0[l];
+            const double ke = 0.5 * (0.5 * (a * a + b * b) + 0.5 * (c * c + d * d) + 0.5 * (e * e + wu * wu)) / rho;
+            const double pres = pref[l] + pref[l] * expm1(kGamma * log1p((double)t[l] / rtref[l]));
+            acc += (ke + pres / (kGamma - 1.0) + rho * kGrav * zc[l]) * vol[l];
+        }
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// Sum n partials in a fixed order: thread t takes t, t+BLOCK, ... with a
+// Neumaier-compensated running sum, then a fixed tree over the block.
+__global__ __launch_bounds__(BLOCK) void k_sum_partials(const double *__restrict__ part, int n,
+                                                        double *__restrict__ out)
+{
+    __shared__ double sh[BLOCK];
+    double s = 0.0, c = 0.0;
+    for (int q = threadIdx.x; q < n; q += BLOCK) {
+        const double x = part[q];
+        const double t = s + x;
+        c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
+        s = t;
+    }
+    const double tot = block_sum(s + c, sh);
+    if (threadIdx.x == 0) out[0] = tot;
+}
+
+// --------------------------------------------------------------------------
+// dispatch
+// --------------------------------------------------------------------------
+inline int nblocks(const Geom &g) { return (g.nx * g.ny + CPB - 1) / CPB; }
+
+template <template <typename, typename, class, int> class F, typename... Args>
+hipError_t dispatch(int prec, int layout, int L, Args &&...args)
+{
+    auto go = [&](auto tag_t, auto tag_s) -> hipError_t {
+        using T = decltype(tag_t);
+        using S = decltype(tag_s);
+        switch ((layout == 1 ? 100 : 0) + L) {
+        case 102: return F<T, S, KIJ, 2>::run(args...);
+        case 104: return F<T, S, KIJ, 4>::run(args...);
+        case 108: return F<T, S, KIJ, 8>::run(args...);
+        case 2: return F<T, S, IJK, 2>::run(args...);
+        case 4: return F<T, S, IJK, 4>::run(args...);
+        case 8: return F<T, S, IJK, 8>::run(args...);
+        default: return hipErrorInvalidValue;
+        }
+    };
+    switch (prec) {
+    case 0: return go(double(), double());
+    case 1: return go(float(), float());
+    case 2: return go(float(), double());
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, typename S, class Lay, int L>
+struct RunPrep {
+    static hipError_t run(const Geom &g, const double *vm, const void *const *st,
+                          void *const *pr, hipStream_t s)
+    {
+        hipLaunchKernelGGL((k_slow_prep<T, Lay, L>), dim3(nblocks(g)), dim3(BLOCK), 0, s, g, vm,
+                           (const T *)st[0], (const T *)st[1], (const T *)st[2], (const T *)st[3],
+                           (const T *)st[4], (T *)pr[0], (T *)pr[1], (T *)pr[2], (T *)pr[3],
+                           (T *)pr[4], (T *)pr[5]);
+        return hipGetLastError();
+    }
+};
+
+template <typename T, typename S, class Lay, int L>
+struct RunFlux {
+    static hipError_t run(const Geom &g, const double *vm, const void *const *uvw,
+                          const void *const *sp, void *const *out, hipStream_t s)
+    {
+        hipLaunchKernelGGL((k_slow_flux<T, Lay, L>), dim3(nblocks(g)), dim3(BLOCK), 0, s, g, vm,
+                           (const T *)uvw[0], (const T *)uvw[1], (const T *)uvw[2],
+                           (const T *)sp[0], (const T *)sp[1], (const T *)sp[2], (const T *)sp[3],
+                           (T *)out[0], (T *)out[1], (T *)out[2], (T *)out[3]);
+        return hipGetLastError();
+    }
+};
+
+template <typename T, typename S, class Lay, int L>
+struct RunShort {
+    static hipError_t run(const Geom &g, const double *vm, const void *const *in, void *const *out,
+                          const void *const *sl, double dtau, hipStream_t s)
+    {
+        hipLaunchKernelGGL((k_short_step<T, S, Lay, L>), dim3(nblocks(g)), dim3(BLOCK), 0, s, g,
+                           vm, dtau, (const T *)in[0], (const T *)in[1], (const T *)in[2],
+                           (const T *)in[3], (const T *)in[4], (T *)out[0], (T *)out[1],
+                           (T *)out[2], (T *)out[3], (T *)out[4], (const T *)sl[0],
+                           (const T *)sl[1], (const T *)sl[2], (const T *)sl[3], (const T *)sl[4],
+                           (const T *)sl[5], (const T *)sl[6]);
+        return hipGetLastError();
+    }
+};
+
+template <typename T, typename S, class Lay, int L>
+struct RunMass {
+    static hipError_t run(const Geom &g, const double *vm, const void *rp, double *part,
+                          double *out, hipStream_t s)
+    {
+        const int nb = nblocks(g);
+        hipLaunchKernelGGL((k_mass_partial<T, Lay, L>), dim3(nb), dim3(BLOCK), 0, s, g, vm,
+                           (const T *)rp, part);
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(BLOCK), 0, s, (const double *)part, nb,
+                           out);
+        return hipGetLastError();
+    }
+};
+
+template <typename T, typename S, class Lay, int L>
+struct RunEnergy {
+    static hipError_t run(const Geom &g, const double *vm, const void *const *st, double *part,
+                          double *out, hipStream_t s)
+    {
+        const int nb = nblocks(g);
+        hipLaunchKernelGGL((k_energy_partial<T, Lay, L>), dim3(nb), dim3(BLOCK), 0, s, g, vm,
+                           (const T *)st[0], (const T *)st[1], (const T *)st[2], (const T *)st[3],
+                           (const T *)st[4], part);
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(BLOCK), 0, s, (const double *)part, nb,
+                           out);
+        return hipGetLastError();
+    }
+};
+
+}  // namespace
+
+hipError_t launch_slow_prep(int prec, int layout, const Geom &g, const double *vm,
+                            const void *const st[5], void *const prep[6], hipStream_t s)
+{
+    return dispatch<RunPrep>(prec, layout, g.nz / SEG, g, vm, st, prep, s);
+}
+
+hipError_t launch_slow_flux(int prec, int layout, const Geom &g, const double *vm,
+                            const void *const uvw[3], const void *const spec[4],
+                            void *const out[4], hipStream_t s)
+{
+    return dispatch<RunFlux>(prec, layout, g.nz / SEG, g, vm, uvw, spec, out, s);
+}
+
+hipError_t launch_short_step(int prec, int layout, const Geom &g, const double *vm,
+                             const void *const in[5], void *const out[5],
+                             const void *const slow[7], double dtau, hipStream_t s)
+{
+    return dispatch<RunShort>(prec, layout, g.nz / SEG, g, vm, in, out, slow, dtau, s);
+}
+
+int mass_partials(const Geom &g) { return nblocks(g); }
+
+hipError_t launch_mass(int prec, int layout, const Geom &g, const double *vm, const void *rp,
+                       double *partials, double *out, hipStream_t s)
+{
+    return dispatch<RunMass>(prec, layout, g.nz / SEG, g, vm, rp, partials, out, s);
+}
+
+hipError_t launch_energy(int prec, int layout, const Geom &g, const double *vm,
+                         const void *const st[5], double *partials, double *out, hipStream_t s)
+{
+    return dispatch<RunEnergy>(prec, layout, g.nz / SEG, g, vm, st, partials, out, s);
+}
+
+}  // namespace hv

@@ -1,0 +1,168 @@
+"""Python binding of libhevi.so (the C ABI in include/hevi.h).
+
+Argument marshalling only: every step of the time integration runs in the
+HIP kernels of the library.  PyTorch supplies the device workspace (one
+uint8 tensor owned by the Domain) and the stream handle.  If the library is
+not built this module raises on first use; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhevi.so")
+
+HV_OK, HV_ERR_ARG, HV_ERR_HIP, HV_ERR_STATE, HV_ERR_NONFINITE, HV_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+FP64, FP32, MIXED = 0, 1, 2
+IJK, KIJ = 0, 1
+RHO_PTB, RHOU, RHOV, RHOW, RHOTHETA_PTB = 0, 1, 2, 3, 4
+
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "mixed": MIXED}
+LAYOUTS = {"ijk": IJK, "kij": KIJ}
+
+EXPORTS = ("hv_workspace_bytes", "hv_grid_create", "hv_state_init", "hv_step", "hv_state_read",
+           "hv_mass", "hv_grid_destroy", "hv_last_error")
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class HvError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"hevi error {code}: {msg}")
+        self.code = code
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+                ("zeta_faces", _dp), ("terrain", _dp),
+                ("precision", ctypes.c_int32), ("layout", ctypes.c_int32),
+                ("beta", ctypes.c_double), ("div_damp", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load libhevi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                           "(or python -m paper_1710_08616_amd.build_lib)")
+    L = ctypes.CDLL(LIB_PATH)
+    L.hv_workspace_bytes.restype = ctypes.c_size_t
+    L.hv_workspace_bytes.argtypes = [ctypes.POINTER(GridDesc)]
+    L.hv_grid_create.restype = ctypes.c_int
+    L.hv_grid_create.argtypes = [ctypes.POINTER(GridDesc), ctypes.c_void_p, ctypes.c_size_t,
+                                 ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+    L.hv_state_init.restype = ctypes.c_int
+    L.hv_state_init.argtypes = [ctypes.c_void_p, ctypes.POINTER(_dp), _dp, _dp, _dp]
+    L.hv_step.restype = ctypes.c_int
+    L.hv_step.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_int32]
+    L.hv_state_read.restype = ctypes.c_int
+    L.hv_state_read.argtypes = [ctypes.c_void_p, ctypes.c_int32, _dp]
+    L.hv_mass.restype = ctypes.c_int
+    L.hv_mass.argtypes = [ctypes.c_void_p, _dp, _dp]
+    L.hv_grid_destroy.restype = None
+    L.hv_grid_destroy.argtypes = [ctypes.c_void_p]
+    L.hv_last_error.restype = ctypes.c_char_p
+    L.hv_last_error.argtypes = [ctypes.c_void_p]
+    _lib = L
+    return L
+
+
+def make_desc(nx, ny, nz, dx, dy, zf, precision="fp32", layout="kij", beta=0.55):
+    zf = np.ascontiguousarray(zf, dtype=np.float64)
+    d = GridDesc(int(nx), int(ny), int(nz), float(dx), float(dy),
+                 zf.ctypes.data_as(_dp), None,
+                 PRECISIONS[precision] if isinstance(precision, str) else int(precision),
+                 LAYOUTS[layout] if isinstance(layout, str) else int(layout),
+                 float(beta), 0.0)
+    return d, zf
+
+
+def workspace_bytes(desc: GridDesc) -> int:
+    return int(load().hv_workspace_bytes(ctypes.byref(desc)))
+
+
+def last_error(handle=None) -> str:
+    return load().hv_last_error(handle).decode()
+
+
+class Domain:
+    """One grid on the GPU: workspace, state, stepping and read-back.
+
+    ``state`` is any object with nx, ny, nz, dx, dy, zf, beta attributes (and
+    rho_ref, rt_ref, p_ref, fields when it is also used to initialise).
+    """
+
+    def __init__(self, state, precision="fp32", layout="kij", device="cuda", stream=None,
+                 init=True):
+        import torch
+        self._torch = torch
+        L = load()
+        self.nx, self.ny, self.nz = int(state.nx), int(state.ny), int(state.nz)
+        self.desc, self._zf = make_desc(state.nx, state.ny, state.nz, state.dx, state.dy, state.zf,
+                                        precision, layout, getattr(state, "beta", 0.55))
+        nbytes = workspace_bytes(self.desc)
+        if nbytes == 0:
+            raise HvError(HV_ERR_ARG, last_error())
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
+        h = ctypes.c_void_p()
+        rc = L.hv_grid_create(ctypes.byref(self.desc), ctypes.c_void_p(self.workspace.data_ptr()),
+                              nbytes, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if rc != HV_OK:
+            raise HvError(rc, last_error())
+        self.handle = h
+        if init:
+            self.init(state.fields, state.rho_ref, state.rt_ref, state.p_ref)
+
+    # -- ABI wrappers -------------------------------------------------------
+    def _check(self, rc):
+        if rc != HV_OK:
+            raise HvError(rc, last_error(self.handle))
+        return rc
+
+    def init(self, fields: Sequence[np.ndarray], rho_ref, rt_ref, p_ref):
+        arrs = [np.ascontiguousarray(f, dtype=np.float64) for f in fields]
+        ptrs = (_dp * 5)(*[a.ctypes.data_as(_dp) for a in arrs])
+        refs = [np.ascontiguousarray(r, dtype=np.float64) for r in (rho_ref, rt_ref, p_ref)]
+        return self._check(load().hv_state_init(self.handle, ptrs,
+                                                *[r.ctypes.data_as(_dp) for r in refs]))
+
+    def step(self, dt: float, n_long: int, n_short: int):
+        return self._check(load().hv_step(self.handle, float(dt), int(n_long), int(n_short)))
+
+    def read(self, field: int) -> np.ndarray:
+        nzf = self.nz + 1 if field == RHOW else self.nz
+        out = np.empty((nzf, self.ny, self.nx), dtype=np.float64)
+        self._check(load().hv_state_read(self.handle, int(field), out.ctypes.data_as(_dp)))
+        return out
+
+    def read_all(self):
+        return [self.read(f) for f in range(5)]
+
+    def mass(self, energy: bool = False):
+        m = ctypes.c_double()
+        e = ctypes.c_double()
+        self._check(load().hv_mass(self.handle, ctypes.byref(m),
+                                   ctypes.byref(e) if energy else None))
+        return (m.value, e.value) if energy else m.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().hv_grid_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

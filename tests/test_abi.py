@@ -1,0 +1,102 @@
+"""The C-ABI library loads and exports every function include/hevi.h declares;
+host-side argument validation works without a GPU (no compute calls)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "hevi.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hv_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def hv():
+    from paper_1710_08616_amd import hevi
+    if not os.path.exists(hevi.LIB_PATH):
+        from paper_1710_08616_amd import build_lib
+        build_lib.build()
+    hevi.load()
+    return hevi
+
+
+def test_every_declared_symbol_is_exported(hv):
+    names = _declared()
+    assert set(names) == set(hv.EXPORTS)
+    lib = ctypes.CDLL(hv.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def _desc(hv, **kw):
+    from paper_1710_08616_amd import inputs
+    a = dict(nx=16, ny=12, nz=32, dx=2000.0, dy=2000.0, zf=inputs.levels(32),
+             precision="fp32", layout="kij", beta=0.55)
+    a.update(kw)
+    return hv.make_desc(**a)
+
+
+def test_workspace_bytes_scales_with_precision(hv):
+    d32, _z = _desc(hv)
+    d64, _z2 = _desc(hv, precision="fp64")
+    b32, b64 = hv.workspace_bytes(d32), hv.workspace_bytes(d64)
+    n = 16 * 12 * 32
+    assert b32 >= 25 * n * 4 and b64 >= 25 * n * 8
+    assert b64 > b32
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(nx=2), "nx and ny"), (dict(nz=40, zf=np.linspace(0, 1e4, 41)), "nz must be"),
+    (dict(dx=0.0), "dx and dy"), (dict(beta=0.4), "beta"), (dict(precision=7), "precision"),
+    (dict(layout=5), "layout"), (dict(zf=-np.linspace(0, 1e4, 33)), "zeta_faces"),
+])
+def test_invalid_descriptions_are_rejected(hv, kw, needle):
+    d, _z = _desc(hv, **kw)
+    assert hv.workspace_bytes(d) == 0
+    assert needle in hv.last_error()
+    h = ctypes.c_void_p()
+    rc = hv.load().hv_grid_create(ctypes.byref(d), ctypes.c_void_p(256), 1 << 30, None,
+                                  ctypes.byref(h))
+    assert rc == hv.HV_ERR_ARG and not h.value
+
+
+def test_create_rejects_short_or_misaligned_workspace(hv):
+    d, _z = _desc(hv)
+    n = hv.workspace_bytes(d)
+    h = ctypes.c_void_p()
+    L = hv.load()
+    assert L.hv_grid_create(ctypes.byref(d), ctypes.c_void_p(4096), n - 1, None,
+                            ctypes.byref(h)) == hv.HV_ERR_ARG
+    assert "too small" in hv.last_error()
+    assert L.hv_grid_create(ctypes.byref(d), ctypes.c_void_p(4096 + 8), n, None,
+                            ctypes.byref(h)) == hv.HV_ERR_ARG
+    assert L.hv_grid_create(ctypes.byref(d), None, n, None, ctypes.byref(h)) == hv.HV_ERR_ARG
+
+
+def test_unbuilt_features_report_unsupported(hv):
+    d, _z = _desc(hv)
+    terr = np.zeros(16 * 12)
+    d.terrain = terr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    h = ctypes.c_void_p()
+    rc = hv.load().hv_grid_create(ctypes.byref(d), ctypes.c_void_p(4096), 1 << 40, None,
+                                  ctypes.byref(h))
+    assert rc == hv.HV_ERR_UNSUPPORTED
+    d2, _z2 = _desc(hv)
+    d2.div_damp = 0.1
+    assert hv.load().hv_grid_create(ctypes.byref(d2), ctypes.c_void_p(4096), 1 << 40, None,
+                                    ctypes.byref(h)) == hv.HV_ERR_UNSUPPORTED
+
+
+def test_null_handle_calls_fail_cleanly(hv):
+    L = hv.load()
+    assert L.hv_step(None, 1.0, 1, 1) == hv.HV_ERR_ARG
+    assert L.hv_state_read(None, 0, None) == hv.HV_ERR_ARG
+    assert L.hv_mass(None, None, None) == hv.HV_ERR_ARG
+    L.hv_grid_destroy(None)
+    assert "handle" in hv.last_error()

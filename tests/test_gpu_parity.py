@@ -1,0 +1,178 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Tolerances:
+- float64 path: max |gpu - oracle| <= 1e-11 x (field range) after the
+  64x64x32 warm-bubble run (10 long steps); the kernels use the same
+  formulas with contraction off, differing only in the column solver
+  (partitioned cyclic reduction vs Thomas) and in reciprocal forms.
+- float32 / mixed paths: 10x the divergence of a twin oracle run that keeps
+  every stored field in binary32 (oracle f32_storage mode, input rounded),
+  per field, in max norm.
+"""
+import numpy as np
+import pytest
+
+from paper_1710_08616_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hv():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1710_08616_amd import hevi
+    hevi.load()
+    return hevi
+
+
+def _rel(a, b):
+    r = np.ptp(b)
+    return np.abs(a - b).max() / (r if r > 0 else 1.0)
+
+
+def _run(hv, s, prec, n_long=None, layout="kij", n_short=None):
+    d = hv.Domain(s, precision=prec, layout=layout)
+    d.step(s.dt, s.n_long if n_long is None else n_long, s.n_short if n_short is None else n_short)
+    out = d.read_all()
+    m = d.mass()
+    d.close()
+    return out, m
+
+
+def test_fp64_small_workload_matches_oracle(hv, oracle):
+    s = inputs.workload("small")          # 64x64x32, 10 long steps, 4 short steps/stage
+    print("case: small fp64 kij", flush=True)
+    ref = oracle.step(s)
+    got, m = _run(hv, s, "fp64")
+    for name, a, b in zip(inputs.FIELD_NAMES, got, ref):
+        assert _rel(a, b) <= 1e-11, (name, _rel(a, b))
+    s2 = s.copy()
+    s2.fields = ref
+    assert abs(m - oracle.mass(s2)) <= 1e-14 * m
+
+
+@pytest.mark.parametrize("nz,n_short", [(32, 3), (64, 6), (128, 2)])
+def test_fp64_ragged_grid_matches_oracle(hv, oracle, nz, n_short):
+    """nx*ny = 260 columns: 16 full blocks and a partial one."""
+    s = inputs.make_state(20, 13, nz, seed=77, n_short=n_short, bubbles=[(2e4, 1.3e4, 4e3, 6e3)],
+                          noise=0.5)
+    print(f"case: ragged 20x13x{nz} fp64", flush=True)
+    ref = oracle.step(s, n_long=3)
+    got, _ = _run(hv, s, "fp64", n_long=3)
+    for name, a, b in zip(inputs.FIELD_NAMES, got, ref):
+        assert _rel(a, b) <= 1e-11, (name, _rel(a, b))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+def test_reduced_precision_small_workload_within_twin_tolerance(hv, oracle, prec):
+    s = inputs.workload("small")
+    print(f"case: small {prec} kij", flush=True)
+    ref = oracle.step(s)
+    twin = oracle.step(s.as_f32(), f32_storage=True)
+    got, m = _run(hv, s, prec)
+    for name, a, b, t in zip(inputs.FIELD_NAMES, got, ref, twin):
+        tol = 10.0 * _rel(t, b)
+        assert _rel(a, b) <= tol, (name, _rel(a, b), tol)
+        assert np.all(np.isfinite(a))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
+@pytest.mark.parametrize("layout", ["kij", "ijk"])
+def test_rest_state_stays_zero(hv, prec, layout):
+    s = inputs.rest_state(16, 8, 32, n_short=3)
+    print(f"case: rest {prec} {layout}", flush=True)
+    got, _ = _run(hv, s, prec, n_long=3, layout=layout, n_short=3)
+    for f in got:
+        assert np.all(f == 0.0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
+def test_uniform_flow_bitwise_steady(hv, prec):
+    s = inputs.rest_state(16, 8, 64)
+    s.fields[1][:] = (s.rho_ref * 10.0)[:, None, None]
+    s.fields[2][:] = (s.rho_ref * -3.0)[:, None, None]
+    print(f"case: uniform flow {prec}", flush=True)
+    d = hv.Domain(s, precision=prec)
+    first = d.read_all()
+    d.step(10.0, 3, 4)
+    got = d.read_all()
+    d.close()
+    for a, b in zip(first, got):
+        assert np.array_equal(a, b)
+
+
+def test_layouts_agree_bitwise(hv):
+    s = inputs.workload("small")
+    print("case: small fp64 ijk vs kij", flush=True)
+    a, ma = _run(hv, s, "fp64", n_long=3, layout="kij")
+    b, mb = _run(hv, s, "fp64", n_long=3, layout="ijk")
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-14), ("mixed", 1e-11), ("fp32", 1e-11)])
+def test_mass_conserved_every_long_step(hv, prec, tol):
+    s = inputs.workload("small")
+    print(f"case: mass {prec}", flush=True)
+    d = hv.Domain(s, precision=prec)
+    m0 = d.mass()
+    for _ in range(5):
+        d.step(s.dt, 2, s.n_short)
+        m = d.mass()
+        assert abs(m - m0) <= tol * m0, (m, m0)
+    d.close()
+
+
+def test_checkpoint_resume_is_bitwise(hv):
+    s = inputs.workload("small")
+    print("case: checkpoint/resume", flush=True)
+    d = hv.Domain(s, precision="fp32")
+    d.step(s.dt, 4, s.n_short)
+    full, _ = None, None
+    d.step(s.dt, 4, s.n_short)
+    full = d.read_all()
+    d.close()
+    d1 = hv.Domain(s, precision="fp32")
+    d1.step(s.dt, 4, s.n_short)
+    mid = d1.read_all()
+    d1.close()
+    s2 = s.copy()
+    s2.fields = mid
+    d2 = hv.Domain(s2, precision="fp32")
+    d2.step(s.dt, 4, s.n_short)
+    res = d2.read_all()
+    d2.close()
+    for a, b in zip(full, res):
+        assert np.array_equal(a, b)
+
+
+def test_error_paths(hv):
+    s = inputs.workload("small")
+    d = hv.Domain(s, precision="fp32", init=False)
+    with pytest.raises(hv.HvError) as e:
+        d.step(10.0, 1, 4)
+    assert e.value.code == hv.HV_ERR_STATE
+    with pytest.raises(hv.HvError) as e:
+        d.read(0)
+    assert e.value.code == hv.HV_ERR_STATE
+    bad = [f.copy() for f in s.fields]
+    bad[4][3, 2, 1] = np.nan
+    with pytest.raises(hv.HvError) as e:
+        d.init(bad, s.rho_ref, s.rt_ref, s.p_ref)
+    assert e.value.code == hv.HV_ERR_ARG
+    bad = [f.copy() for f in s.fields]
+    bad[3][0, 1, 1] = 1.0
+    with pytest.raises(hv.HvError) as e:
+        d.init(bad, s.rho_ref, s.rt_ref, s.p_ref)
+    assert e.value.code == hv.HV_ERR_ARG
+    d.init(s.fields, s.rho_ref, s.rt_ref, s.p_ref)
+    with pytest.raises(hv.HvError) as e:
+        d.step(-1.0, 1, 4)
+    assert e.value.code == hv.HV_ERR_ARG
+    with pytest.raises(hv.HvError) as e:
+        d.step(10.0, 1, 0)
+    assert e.value.code == hv.HV_ERR_ARG
+    d.step(10.0, 1, 4)
+    assert np.isfinite(d.mass())
+    d.close()

@@ -1,0 +1,197 @@
+"""Benchmark of the HEVI dynamical-core step on one GPU.
+
+Workload: the 1024x1024x64 warm-bubble domain (16 seeded bubbles of radius
+2-8 km, Gaussian velocity noise of 0.1 m/s in a 10 m/s wind, isothermal
+reference, dx = dy = 2 km, stretched levels to 20 km), RK3 long steps of
+dt = 10 s with 6 HEVI short steps per stage, periodic in x and y.  One
+"step" is one long step of the whole path: 3 slow sweeps, 18 short steps and
+the float64 mass sum.  The primary number is the float32 path; the mixed
+(float32 sweeps, float64 column solve) and float64 paths are timed on the same
+state for the speedup over the plain float64 step.
+
+Prints one JSON line.  Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s + achieved HBM GB/s (% peak), FP32/mixed vs FP64 step, 1 GPU"
+HBM_PEAK_GBS = 8000.0
+BYTES = {"fp32": 4, "mixed": 4, "fp64": 8}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def model_bytes_per_cell(b: int, n_short: int) -> int:
+    """Compulsory bytes per cell per long step: 3 slow sweeps (read 5 state,
+    write 7), 3*n short steps (read 5 state + 4 tendencies + 3 stage
+    coefficients, write 5), one mass sum (read rho')."""
+    return b * (3 * 12 + 3 * n_short * 17 + 1)
+
+
+def short_step_bytes(b: int, cells: int) -> int:
+    return 17 * b * cells
+
+
+def kernel_digest() -> str:
+    src = os.path.join(ROOT, "paper_1710_08616_amd", "csrc", "hevi_kernels.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def read_traffic(prec: str):
+    """HBM bytes per short-step launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "short_step_large_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("traffic:"):
+            try:
+                rec = json.loads(line[len("traffic:"):])
+            except ValueError:
+                continue
+            if rec.get("kernel_sha") == kernel_digest() and rec.get("precision") == prec:
+                return rec.get("bytes_per_launch")
+    return None
+
+
+def time_precision(hevi, s, prec, steps, warmup, layout="kij"):
+    import torch
+    log(f"[bench] {prec}: init {s.nx}x{s.ny}x{s.nz}")
+    d = hevi.Domain(s, precision=prec, layout=layout)
+    if warmup:
+        d.step(s.dt, warmup, s.n_short)
+    m0 = d.mass()
+    torch.cuda.synchronize()
+    d.trace(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(d.stream)
+    d.step(s.dt, steps, s.n_short)
+    e1.record(d.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    kern = d.trace_read()
+    d.trace(False)
+    m1 = d.mass()
+    d.close()
+    del d
+    torch.cuda.empty_cache()
+    cells = s.cells
+    res = {
+        "ms_per_step": ms / steps,
+        "cell_updates_per_s": cells * steps / (ms * 1e-3),
+        "model_gbps": model_bytes_per_cell(BYTES[prec], s.n_short) * cells * steps / (ms * 1e-3) / 1e9,
+        "mass_drift_rel": abs(m1 - m0) / m0,
+        "kernels_ms_avg": {k: (v[0] / v[1] if v[1] else None) for k, v in kern.items()},
+        "kernels_launches": {k: v[1] for k, v in kern.items()},
+        "kernels_ms_total": {k: v[0] for k, v in kern.items()},
+    }
+    log(f"[bench] {prec}: {res['ms_per_step']:.3f} ms/step, "
+        f"{res['cell_updates_per_s']:.3e} cell-updates/s, model {res['model_gbps']:.0f} GB/s")
+    return res
+
+
+def cpu_baseline(steps: int = 4, n: int = 512):
+    """The FP64 oracle on a bounded sample of the same workload: an n x n x 64
+    domain from the same generator (16 bubbles), `steps` long steps."""
+    from oracle import oracle
+    from paper_1710_08616_amd import inputs
+    bub = inputs.random_bubbles(1711, 16, n * 2000.0, n * 2000.0)
+    s = inputs.make_state(n, n, 64, seed=1711, bubbles=bub, dt=10.0, n_short=6)
+    oracle.lib()
+    t0 = time.perf_counter()
+    oracle.step(s, n_long=steps)
+    sec = time.perf_counter() - t0
+    return {"value": s.cells * steps / sec, "unit": "cell-updates/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"{n}x{n}x64 sub-domain of the same generator, {steps} long steps "
+                      f"(n=6), {sec:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precisions", default="fp32,mixed,fp64")
+    ap.add_argument("--layout", default="kij")
+    ap.add_argument("--workload", default="large")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the step is built and measured on a single "
+              "MI355X (multi-GPU decomposition is design-only); run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1710_08616_amd import hevi, inputs
+    hevi.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    t0 = time.time()
+    s = inputs.workload(args.workload)
+    log(f"[bench] state {s.nx}x{s.ny}x{s.nz} generated in {time.time() - t0:.1f} s")
+    precs = [p for p in args.precisions.split(",") if p]
+    res = {p: time_precision(hevi, s, p, args.steps, args.warmup, args.layout) for p in precs}
+    primary = "fp32" if "fp32" in res else precs[0]
+    r = res[primary]
+    b = BYTES[primary]
+    short_ms = r["kernels_ms_avg"]["short_step"]
+    ach = short_step_bytes(b, s.cells) / (short_ms * 1e-3) / 1e9
+    traffic = read_traffic(primary)
+    roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "short_step", "bytes_per_launch": short_step_bytes(b, s.cells),
+                "launch_ms_avg": round(short_ms, 4)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle baseline")
+        cpu = cpu_baseline()
+        log(f"[bench] oracle: {cpu['value']:.3e} cell-updates/s on {cpu['cores']} threads")
+    out = {
+        "metric": METRIC,
+        "value": r["cell_updates_per_s"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if primary == "fp32" else ("f32+f64" if primary == "mixed" else "f64"),
+        "data": "synthetic",
+        "config": {"workload": f"{s.nx}x{s.ny}x{s.nz} warm bubbles + noise, dt=10 s, "
+                               f"{s.n_short} short steps/stage",
+                   "nx": s.nx, "ny": s.ny, "nz": s.nz, "n_short": s.n_short, "dt": s.dt,
+                   "precision": primary, "layout": args.layout, "parallelism": "1 GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "model_gbps": r["model_gbps"],
+        "model_frac_of_peak": r["model_gbps"] / HBM_PEAK_GBS,
+        "per_precision": res,
+    }
+    if "fp64" in res:
+        for p in res:
+            if p != "fp64":
+                out[f"speedup_{p}_vs_fp64"] = res["fp64"]["ms_per_step"] / res[p]["ms_per_step"]
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

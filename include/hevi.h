@@ -116,6 +116,17 @@ int hv_state_read(hv_grid_t g, int32_t field, double *host_out);
  * Synchronises the stream. */
 int hv_mass(hv_grid_t g, double *mass_out, double *energy_out);
 
+/* Kernel timing with HIP events on the grid's stream, a measurement aid.
+ * hv_trace(g, 1) zeroes the totals and records an event pair around every
+ * kernel launch that follows; hv_trace(g, 0) stops recording.
+ * hv_trace_read synchronises the stream, folds the recorded pairs into
+ * per-kind totals and returns the total milliseconds and launch count of
+ * one kind (a "launch" of HV_K_MASS is its two-kernel reduction).  Either
+ * output pointer may be NULL. */
+enum { HV_K_SLOW_PREP = 0, HV_K_SLOW_FLUX = 1, HV_K_SHORT_STEP = 2, HV_K_MASS = 3, HV_K_COUNT = 4 };
+int hv_trace(hv_grid_t g, int32_t on);
+int hv_trace_read(hv_grid_t g, int32_t kind, double *ms_total, int64_t *launches);
+
 /* Release the handle (never the caller's workspace).  NULL is a no-op. */
 void hv_grid_destroy(hv_grid_t g);
 

@@ -52,6 +52,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_GAMMA 1.4
 
@@ -786,4 +789,14 @@ double or_energy(const or_grid *g, const double *const st[5])
             }
     }
     return s + comp;
+}
+
+/* Number of OpenMP threads the parallel loops use (1 without OpenMP). */
+int or_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -73,6 +73,8 @@ def lib():
         L.or_mass.argtypes = [ctypes.c_void_p, _dp]
         L.or_energy.restype = ctypes.c_double
         L.or_energy.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.or_threads.restype = ctypes.c_int
+        L.or_threads.argtypes = []
         _lib = L
     return _lib
 
@@ -155,6 +157,11 @@ def short_step(s, slow, dtau, fields=None, grav: float = GRAV) -> List[np.ndarra
     if rc != OK:
         raise RuntimeError(f"or_short_step failed: {rc}")
     return out
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().or_threads())
 
 
 def koren_phi(dm: float, dp: float) -> float:

@@ -48,6 +48,20 @@ struct hv_grid {
     bool have_state = false;
     bool any_nonfinite = false;
     std::string err = "no error";
+
+    // kernel timing (hv_trace)
+    struct Pending { int kind; hipEvent_t a, b; };
+    bool tracing = false;
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    double trace_ms[HV_K_COUNT] = {};
+    int64_t trace_n[HV_K_COUNT] = {};
+
+    ~hv_grid()
+    {
+        for (auto &p : pending) { pool.push_back(p.a); pool.push_back(p.b); }
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
 };
 
 namespace {
@@ -182,6 +196,53 @@ void fill_vmet(hv_grid *g, const double *rho, const double *rt, const double *p,
 
 hipError_t sync(hv_grid *g) { return hipStreamSynchronize(g->stream); }
 
+hipError_t take_event(hv_grid *g, hipEvent_t *e)
+{
+    if (!g->pool.empty()) {
+        *e = g->pool.back();
+        g->pool.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(e);
+}
+
+// Run one launch, bracketed by events when tracing is on.
+template <class F>
+hipError_t traced(hv_grid *g, int kind, F &&launch)
+{
+    if (!g->tracing) return launch();
+    hipEvent_t a, b;
+    hipError_t e = take_event(g, &a);
+    if (e != hipSuccess) return e;
+    e = take_event(g, &b);
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(a, g->stream);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, g->stream);
+    if (e != hipSuccess) return e;
+    g->pending.push_back({kind, a, b});
+    return hipSuccess;
+}
+
+hipError_t fold_trace(hv_grid *g)
+{
+    hipError_t e = sync(g);
+    if (e != hipSuccess) return e;
+    for (auto &p : g->pending) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, p.a, p.b);
+        if (e != hipSuccess) return e;
+        g->trace_ms[p.kind] += ms;
+        g->trace_n[p.kind] += 1;
+        g->pool.push_back(p.a);
+        g->pool.push_back(p.b);
+    }
+    g->pending.clear();
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -310,12 +371,16 @@ int hv_step(hv_grid_t g, double dt, int32_t n_long, int32_t n_short)
             void *const *in = g->state[stage_in];
             const void *st[5] = {in[0], in[1], in[2], in[3], in[4]};
             void *prep[6] = {g->spec[0], g->spec[1], g->spec[2], g->slow[4], g->slow[5], g->slow[6]};
-            hipError_t e = hv::launch_slow_prep(g->prec, g->layout, g->geom, g->vm, st, prep, g->stream);
+            hipError_t e = traced(g, HV_K_SLOW_PREP, [&] {
+                return hv::launch_slow_prep(g->prec, g->layout, g->geom, g->vm, st, prep, g->stream);
+            });
             if (e != hipSuccess) return hip_fail(g, e, "slow sweep (prep)");
             const void *uvw[3] = {in[1], in[2], in[3]};
             const void *spec[4] = {g->spec[0], g->spec[1], g->spec[2], g->slow[4]};
             void *fl[4] = {g->slow[0], g->slow[1], g->slow[2], g->slow[3]};
-            e = hv::launch_slow_flux(g->prec, g->layout, g->geom, g->vm, uvw, spec, fl, g->stream);
+            e = traced(g, HV_K_SLOW_FLUX, [&] {
+                return hv::launch_slow_flux(g->prec, g->layout, g->geom, g->vm, uvw, spec, fl, g->stream);
+            });
             if (e != hipSuccess) return hip_fail(g, e, "slow sweep (flux)");
             const double dtau = dt * frac[s] / n_short;
             int src = P;
@@ -324,16 +389,20 @@ int hv_step(hv_grid_t g, double dt, int32_t n_long, int32_t n_short)
                 const void *sin[5], *sl[7];
                 for (int f = 0; f < 5; ++f) sin[f] = g->state[src][f];
                 for (int f = 0; f < 7; ++f) sl[f] = g->slow[f];
-                e = hv::launch_short_step(g->prec, g->layout, g->geom, g->vm, sin, g->state[dst], sl,
-                                          dtau, g->stream);
+                e = traced(g, HV_K_SHORT_STEP, [&] {
+                    return hv::launch_short_step(g->prec, g->layout, g->geom, g->vm, sin, g->state[dst],
+                                                 sl, dtau, g->stream);
+                });
                 if (e != hipSuccess) return hip_fail(g, e, "short step");
                 src = dst;
             }
             stage_in = src;
         }
         g->cur = stage_in;
-        hipError_t e = hv::launch_mass(g->prec, g->layout, g->geom, g->vm,
-                                       g->state[g->cur][HV_RHO_PTB], g->partials, g->sums, g->stream);
+        hipError_t e = traced(g, HV_K_MASS, [&] {
+            return hv::launch_mass(g->prec, g->layout, g->geom, g->vm, g->state[g->cur][HV_RHO_PTB],
+                                   g->partials, g->sums, g->stream);
+        });
         if (e != hipSuccess) return hip_fail(g, e, "mass sum");
     }
     return HV_OK;
@@ -391,6 +460,29 @@ int hv_mass(hv_grid_t g, double *mass_out, double *energy_out)
         g->any_nonfinite = true;
     }
     if (g->any_nonfinite) return fail(g, HV_ERR_NONFINITE, "mass sum is not finite");
+    return HV_OK;
+}
+
+int hv_trace(hv_grid_t g, int32_t on)
+{
+    if (!g) return fail(nullptr, HV_ERR_ARG, "handle is NULL");
+    if (on) {
+        hipError_t e = fold_trace(g);
+        if (e != hipSuccess) return hip_fail(g, e, "hv_trace");
+        for (int k = 0; k < HV_K_COUNT; ++k) { g->trace_ms[k] = 0.0; g->trace_n[k] = 0; }
+    }
+    g->tracing = on != 0;
+    return HV_OK;
+}
+
+int hv_trace_read(hv_grid_t g, int32_t kind, double *ms_total, int64_t *launches)
+{
+    if (!g) return fail(nullptr, HV_ERR_ARG, "handle is NULL");
+    if (kind < 0 || kind >= HV_K_COUNT) return fail(g, HV_ERR_ARG, "unknown kernel kind");
+    hipError_t e = fold_trace(g);
+    if (e != hipSuccess) return hip_fail(g, e, "hv_trace_read");
+    if (ms_total) *ms_total = g->trace_ms[kind];
+    if (launches) *launches = g->trace_n[kind];
     return HV_OK;
 }
 

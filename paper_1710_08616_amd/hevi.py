@@ -25,7 +25,10 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "mixed": MIXED}
 LAYOUTS = {"ijk": IJK, "kij": KIJ}
 
 EXPORTS = ("hv_workspace_bytes", "hv_grid_create", "hv_state_init", "hv_step", "hv_state_read",
-           "hv_mass", "hv_grid_destroy", "hv_last_error")
+           "hv_mass", "hv_trace", "hv_trace_read", "hv_grid_destroy", "hv_last_error")
+K_SLOW_PREP, K_SLOW_FLUX, K_SHORT_STEP, K_MASS = 0, 1, 2, 3
+KERNEL_KINDS = {"slow_prep": K_SLOW_PREP, "slow_flux": K_SLOW_FLUX, "short_step": K_SHORT_STEP,
+                "mass": K_MASS}
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -69,6 +72,11 @@ def load():
     L.hv_state_read.argtypes = [ctypes.c_void_p, ctypes.c_int32, _dp]
     L.hv_mass.restype = ctypes.c_int
     L.hv_mass.argtypes = [ctypes.c_void_p, _dp, _dp]
+    L.hv_trace.restype = ctypes.c_int
+    L.hv_trace.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    L.hv_trace_read.restype = ctypes.c_int
+    L.hv_trace_read.argtypes = [ctypes.c_void_p, ctypes.c_int32, _dp,
+                                ctypes.POINTER(ctypes.c_int64)]
     L.hv_grid_destroy.restype = None
     L.hv_grid_destroy.argtypes = [ctypes.c_void_p]
     L.hv_last_error.restype = ctypes.c_char_p
@@ -155,6 +163,19 @@ class Domain:
         self._check(load().hv_mass(self.handle, ctypes.byref(m),
                                    ctypes.byref(e) if energy else None))
         return (m.value, e.value) if energy else m.value
+
+    def trace(self, on: bool):
+        return self._check(load().hv_trace(self.handle, 1 if on else 0))
+
+    def trace_read(self):
+        """{kind: (total ms, launches)} of the kernels recorded since trace(True)."""
+        out = {}
+        for name, kind in KERNEL_KINDS.items():
+            ms = ctypes.c_double()
+            n = ctypes.c_int64()
+            self._check(load().hv_trace_read(self.handle, kind, ctypes.byref(ms), ctypes.byref(n)))
+            out[name] = (ms.value, n.value)
+        return out
 
     def close(self):
         if getattr(self, "handle", None):

@@ -63,21 +63,24 @@ def gaussian(seed: int, component: int, shape, offset=(0, 0, 0), full=None) -> n
     ``shape`` is (nk, nj, ni); ``offset`` shifts the (k, j, i) counters so a
     sub-block reproduces the same numbers as the whole field would; ``full`` is
     the (nz, ny, nx) extent the counters are numbered over (defaults to shape).
+    Generated one k-slab at a time to keep the temporaries small.
     """
     nk, nj, ni = shape
     full = shape if full is None else full
-    k = np.arange(nk, dtype=np.uint64)[:, None, None] + np.uint64(offset[0])
-    j = np.arange(nj, dtype=np.uint64)[None, :, None] + np.uint64(offset[1])
-    i = np.arange(ni, dtype=np.uint64)[None, None, :] + np.uint64(offset[2])
+    out = np.empty((nk, nj, ni))
+    j = np.arange(nj, dtype=np.uint64)[:, None] + np.uint64(offset[1])
+    i = np.arange(ni, dtype=np.uint64)[None, :] + np.uint64(offset[2])
     with np.errstate(over="ignore"):
         base = splitmix64(np.uint64(seed & 0xFFFFFFFFFFFFFFFF) * np.uint64(0x100000001B3)
                           + np.uint64(component))
-        ctr = base + (k * np.uint64(full[1]) + j) * np.uint64(full[2]) + i
-    b1 = splitmix64(ctr)
-    b2 = splitmix64(ctr ^ np.uint64(0xD1B54A32D192ED03))
-    u1 = _uniform01(b1)
-    u2 = _uniform01(b2)
-    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * math.pi * u2)
+        plane = j * np.uint64(full[2]) + i
+        for kk in range(nk):
+            k = np.uint64(kk + offset[0])
+            ctr = base + (k * np.uint64(full[1])) * np.uint64(full[2]) + plane
+            u1 = _uniform01(splitmix64(ctr))
+            u2 = _uniform01(splitmix64(ctr ^ np.uint64(0xD1B54A32D192ED03)))
+            out[kk] = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * math.pi * u2)
+    return out
 
 
 # --------------------------------------------------------------------------
@@ -173,18 +176,25 @@ def bubble_theta(nx, ny, zc, dx, dy, bubbles, amp=2.0) -> np.ndarray:
     """Sum of cos^2 warm bubbles: amp * cos^2(pi r / 2) for r < 1.
 
     ``bubbles`` is a list of (xc, yc, zc, radius); r is the 3D distance
-    (periodic in x and y) divided by the radius.
+    (periodic in x and y) divided by the radius.  Each bubble is evaluated
+    only on the index box that can hold r < 1.
     """
     lx, ly = nx * dx, ny * dy
-    x = (np.arange(nx) + 0.5) * dx
-    y = (np.arange(ny) + 0.5) * dy
     th = np.zeros((len(zc), ny, nx))
     for (xb, yb, zb, rb) in bubbles:
-        ddx = _periodic_dist(x, xb, lx)[None, None, :]
-        ddy = _periodic_dist(y, yb, ly)[None, :, None]
-        ddz = (zc - zb)[:, None, None]
+        kk = np.nonzero(np.abs(zc - zb) < rb)[0]
+        if kk.size == 0:
+            continue
+        wi = min(nx, 2 * int(math.ceil(rb / dx)) + 3)
+        wj = min(ny, 2 * int(math.ceil(rb / dy)) + 3)
+        ii = (int(math.floor((xb - rb) / dx)) - 1 + np.arange(wi)) % nx
+        jj = (int(math.floor((yb - rb) / dy)) - 1 + np.arange(wj)) % ny
+        ddx = _periodic_dist((ii + 0.5) * dx, xb, lx)[None, None, :]
+        ddy = _periodic_dist((jj + 0.5) * dy, yb, ly)[None, :, None]
+        ddz = (zc[kk] - zb)[:, None, None]
         r = np.sqrt(ddx * ddx + ddy * ddy + ddz * ddz) / rb
-        th += np.where(r < 1.0, amp * np.cos(0.5 * math.pi * np.minimum(r, 1.0)) ** 2, 0.0)
+        box = np.ix_(kk, jj, ii)
+        th[box] += np.where(r < 1.0, amp * np.cos(0.5 * math.pi * np.minimum(r, 1.0)) ** 2, 0.0)
     return th
 
 

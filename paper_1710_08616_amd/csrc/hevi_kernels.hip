@@ -52,6 +52,11 @@ using vec_t = T __attribute__((ext_vector_type(L)));
 
 __device__ __forceinline__ int wrapc(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
+// Block b covers columns 16b .. 16b+15.  (Walking a contiguous eighth of the
+// domain per XCD instead was measured slower: consecutive blocks already put
+// the j-neighbour tiles, 64 blocks apart at nx = 1024, on the same XCD.)
+__device__ __forceinline__ int tile_of_block() { return (int)blockIdx.x; }
+
 // Storage orders of a 3D field with nz levels per column.
 struct KIJ {
     static constexpr bool kContig = true;
@@ -86,19 +91,29 @@ struct Lane {
     {
         return Lay::at(wrapc(i + di, nx), wrapc(j + dj, ny), k0, nx, ny, nz);
     }
-    template <typename T>
+    // Load the lane's L levels of column (i+di, j+dj).  NT = non-temporal:
+    // for data no other column reads in this kernel.
+    template <bool NT = false, typename T>
     __device__ void load(const T *__restrict__ a, int di, int dj, T (&x)[L]) const
     {
         const T *q = a + off(di, dj);
         if constexpr (Lay::kContig) {
-            const vec_t<T, L> t = *reinterpret_cast<const vec_t<T, L> *>(q);
+            const vec_t<T, L> *vq = reinterpret_cast<const vec_t<T, L> *>(q);
+            vec_t<T, L> t;
+            if constexpr (NT) t = __builtin_nontemporal_load(vq);
+            else t = *vq;
 #pragma unroll
             for (int l = 0; l < L; ++l) x[l] = t[l];
         } else {
 #pragma unroll
-            for (int l = 0; l < L; ++l) x[l] = q[(size_t)l * kstride];
+            for (int l = 0; l < L; ++l) {
+                if constexpr (NT) x[l] = __builtin_nontemporal_load(q + (size_t)l * kstride);
+                else x[l] = q[(size_t)l * kstride];
+            }
         }
     }
+    // Store the lane's L levels of the own column (non-temporal: results are
+    // not read again by this kernel).
     template <typename T, typename S>
     __device__ void store(T *__restrict__ a, const S (&x)[L]) const
     {
@@ -107,10 +122,10 @@ struct Lane {
             vec_t<T, L> t;
 #pragma unroll
             for (int l = 0; l < L; ++l) t[l] = (T)x[l];
-            *reinterpret_cast<vec_t<T, L> *>(q) = t;
+            __builtin_nontemporal_store(t, reinterpret_cast<vec_t<T, L> *>(q));
         } else {
 #pragma unroll
-            for (int l = 0; l < L; ++l) q[(size_t)l * kstride] = (T)x[l];
+            for (int l = 0; l < L; ++l) __builtin_nontemporal_store((T)x[l], q + (size_t)l * kstride);
         }
     }
     // per-level constant of the lane's levels (+ offset), as type S
@@ -188,7 +203,7 @@ __global__ __launch_bounds__(BLOCK) void k_slow_prep(
     T *__restrict__ uo, T *__restrict__ vo, T *__restrict__ wo, T *__restrict__ tho,
     T *__restrict__ P0o, T *__restrict__ Cso)
 {
-    const int col = blockIdx.x * CPB + threadIdx.x / SEG;
+    const int col = tile_of_block() * CPB + threadIdx.x / SEG;
     if (col >= g.nx * g.ny) return;
     const Lane<Lay, L> ln(g, col);
 
@@ -196,10 +211,10 @@ __global__ __launch_bounds__(BLOCK) void k_slow_prep(
     ln.load(rp, 0, 0, r0);
     ln.load(rp, -1, 0, rw);
     ln.load(rp, 0, -1, rs);
-    ln.load(U, 0, 0, Uc);
-    ln.load(V, 0, 0, Vc);
-    ln.load(W, 0, 0, Wc);
-    ln.load(tp, 0, 0, tc);
+    ln.template load<true>(U, 0, 0, Uc);
+    ln.template load<true>(V, 0, 0, Vc);
+    ln.template load<true>(W, 0, 0, Wc);
+    ln.template load<true>(tp, 0, 0, tc);
     T rref[L], rtref[L], pref[L], a[L], b[L];
     ln.vmet(vm, VM_RHO, rref);
     ln.vmet(vm, VM_RT, rtref);
@@ -472,7 +487,7 @@ __global__ __launch_bounds__(BLOCK) void k_slow_flux(
     const T *__restrict__ ww, const T *__restrict__ th, T *__restrict__ SU, T *__restrict__ SV,
     T *__restrict__ SW, T *__restrict__ RT)
 {
-    const int col = blockIdx.x * CPB + threadIdx.x / SEG;
+    const int col = tile_of_block() * CPB + threadIdx.x / SEG;
     if (col >= g.nx * g.ny) return;
     const Lane<Lay, L> ln(g, col);
     const T rdx = (T)g.rdx, rdy = (T)g.rdy;
@@ -564,7 +579,7 @@ __global__ __launch_bounds__(BLOCK) void k_short_step(
     const T *__restrict__ SV, const T *__restrict__ SW, const T *__restrict__ RT,
     const T *__restrict__ ths, const T *__restrict__ P0, const T *__restrict__ Cs)
 {
-    const int col = blockIdx.x * CPB + threadIdx.x / SEG;
+    const int col = tile_of_block() * CPB + threadIdx.x / SEG;
     if (col >= g.nx * g.ny) return;
     const Lane<Lay, L> ln(g, col);
     const T dt = (T)dtau_d, rdx = (T)g.rdx, rdy = (T)g.rdy;
@@ -608,10 +623,10 @@ __global__ __launch_bounds__(BLOCK) void k_short_step(
     ln.load(SV, 0, 0, SV0);
     ln.load(SV, 0, 1, SV1);
     T rpc[L], Wc[L], SWc[L], RTc[L];
-    ln.load(rp, 0, 0, rpc);
-    ln.load(W, 0, 0, Wc);
-    ln.load(SW, 0, 0, SWc);
-    ln.load(RT, 0, 0, RTc);
+    ln.template load<true>(rp, 0, 0, rpc);
+    ln.template load<true>(W, 0, 0, Wc);
+    ln.template load<true>(SW, 0, 0, SWc);
+    ln.template load<true>(RT, 0, 0, RTc);
 
     T Up[L], Vp[L], rt[L], tt[L];
 #pragma unroll
@@ -735,22 +750,27 @@ __device__ __forceinline__ double block_sum(double v, double *sh)
     return sh[0];
 }
 
+// Partial sums: block b accumulates the tiles b, b + G, b + 2G, ... (G = grid
+// size, fixed by the domain) in that order, each lane in float64, then a fixed
+// tree over the block.
 template <typename T, class Lay, int L>
 __global__ __launch_bounds__(BLOCK) void k_mass_partial(Geom g, const double *__restrict__ vm,
                                                         const T *__restrict__ rp,
-                                                        double *__restrict__ part)
+                                                        double *__restrict__ part, int ntiles)
 {
     __shared__ double sh[BLOCK];
-    const int col = blockIdx.x * CPB + threadIdx.x / SEG;
+    double vol[L];
     double acc = 0.0;
-    if (col < g.nx * g.ny) {
-        const Lane<Lay, L> ln(g, col);
-        T r[L];
-        double vol[L];
-        ln.load(rp, 0, 0, r);
-        ln.vmet(vm, VM_VOL, vol);
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int col = t * CPB + threadIdx.x / SEG;
+        if (col < g.nx * g.ny) {
+            const Lane<Lay, L> ln(g, col);
+            ln.vmet(vm, VM_VOL, vol);
+            T r[L];
+            ln.template load<true>(rp, 0, 0, r);
 #pragma unroll
-        for (int l = 0; l < L; ++l) acc += (double)r[l] * vol[l];
+            for (int l = 0; l < L; ++l) acc += (double)r[l] * vol[l];
+        }
     }
     const double s = block_sum(acc, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
@@ -760,37 +780,39 @@ template <typename T, class Lay, int L>
 __global__ __launch_bounds__(BLOCK) void k_energy_partial(
     Geom g, const double *__restrict__ vm, const T *__restrict__ rp, const T *__restrict__ U,
     const T *__restrict__ V, const T *__restrict__ W, const T *__restrict__ tp,
-    double *__restrict__ part)
+    double *__restrict__ part, int ntiles)
 {
     __shared__ double sh[BLOCK];
-    const int col = blockIdx.x * CPB + threadIdx.x / SEG;
     double acc = 0.0;
-    if (col < g.nx * g.ny) {
-        const Lane<Lay, L> ln(g, col);
-        T r[L], u0[L], u1[L], v0[L], v1[L], w0[L], t[L];
-        ln.load(rp, 0, 0, r);
-        ln.load(U, 0, 0, u0);
-        ln.load(U, 1, 0, u1);
-        ln.load(V, 0, 0, v0);
-        ln.load(V, 0, 1, v1);
-        ln.load(W, 0, 0, w0);
-        ln.load(tp, 0, 0, t);
-        const T wt = from_above(w0[0]);
-        double vol[L], rref[L], rtref[L], pref[L], zc[L];
-        ln.vmet(vm, VM_VOL, vol);
-        ln.vmet(vm, VM_RHO, rref);
-        ln.vmet(vm, VM_RT, rtref);
-        ln.vmet(vm, VM_P, pref);
-        ln.vmet(vm, VM_ZC, zc);
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int col = t * CPB + threadIdx.x / SEG;
+        if (col < g.nx * g.ny) {
+            const Lane<Lay, L> ln(g, col);
+            T r[L], u0[L], u1[L], v0[L], v1[L], w0[L], th[L];
+            ln.load(rp, 0, 0, r);
+            ln.load(U, 0, 0, u0);
+            ln.load(U, 1, 0, u1);
+            ln.load(V, 0, 0, v0);
+            ln.load(V, 0, 1, v1);
+            ln.load(W, 0, 0, w0);
+            ln.load(tp, 0, 0, th);
+            const T wt = from_above(w0[0]);
+            double vol[L], rref[L], rtref[L], pref[L], zc[L];
+            ln.vmet(vm, VM_VOL, vol);
+            ln.vmet(vm, VM_RHO, rref);
+            ln.vmet(vm, VM_RT, rtref);
+            ln.vmet(vm, VM_P, pref);
+            ln.vmet(vm, VM_ZC, zc);
 #pragma unroll
-        for (int l = 0; l < L; ++l) {
-            const double rho = rref[l] + (double)r[l];
-            const double wu = (l < L - 1) ? (double)w0[l + 1] : (ln.p == SEG - 1 ? 0.0 : (double)wt);
-            const double a = (double)u0[l], b = (double)u1[l], c = (double)v0[l], d = (double)v1[l];
-            const double e = (double)w0[l];
-            const double ke = 0.5 * (0.5 * (a * a + b * b) + 0.5 * (c * c + d * d) + 0.5 * (e * e + wu * wu)) / rho;
-            const double pres = pref[l] + pref[l] * expm1(kGamma * log1p((double)t[l] / rtref[l]));
-            acc += (ke + pres / (kGamma - 1.0) + rho * kGrav * zc[l]) * vol[l];
+            for (int l = 0; l < L; ++l) {
+                const double rho = rref[l] + (double)r[l];
+                const double wu = (l < L - 1) ? (double)w0[l + 1] : (ln.p == SEG - 1 ? 0.0 : (double)wt);
+                const double a = (double)u0[l], b = (double)u1[l], c = (double)v0[l], d = (double)v1[l];
+                const double e = (double)w0[l];
+                const double ke = 0.5 * (0.5 * (a * a + b * b) + 0.5 * (c * c + d * d) + 0.5 * (e * e + wu * wu)) / rho;
+                const double pres = pref[l] + pref[l] * expm1(kGamma * log1p((double)th[l] / rtref[l]));
+                acc += (ke + pres / (kGamma - 1.0) + rho * kGrav * zc[l]) * vol[l];
+            }
         }
     }
     const double s = block_sum(acc, sh);
@@ -818,6 +840,8 @@ __global__ __launch_bounds__(BLOCK) void k_sum_partials(const double *__restrict
 // dispatch
 // --------------------------------------------------------------------------
 inline int nblocks(const Geom &g) { return (g.nx * g.ny + CPB - 1) / CPB; }
+constexpr int kMaxPartials = 1024;
+inline int npartials(const Geom &g) { return nblocks(g) < kMaxPartials ? nblocks(g) : kMaxPartials; }
 
 template <template <typename, typename, class, int> class F, typename... Args>
 hipError_t dispatch(int prec, int layout, int L, Args &&...args)
@@ -889,9 +913,9 @@ struct RunMass {
     static hipError_t run(const Geom &g, const double *vm, const void *rp, double *part,
                           double *out, hipStream_t s)
     {
-        const int nb = nblocks(g);
+        const int nb = npartials(g);
         hipLaunchKernelGGL((k_mass_partial<T, Lay, L>), dim3(nb), dim3(BLOCK), 0, s, g, vm,
-                           (const T *)rp, part);
+                           (const T *)rp, part, nblocks(g));
         hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(BLOCK), 0, s, (const double *)part, nb,
                            out);
         return hipGetLastError();
@@ -903,10 +927,10 @@ struct RunEnergy {
     static hipError_t run(const Geom &g, const double *vm, const void *const *st, double *part,
                           double *out, hipStream_t s)
     {
-        const int nb = nblocks(g);
+        const int nb = npartials(g);
         hipLaunchKernelGGL((k_energy_partial<T, Lay, L>), dim3(nb), dim3(BLOCK), 0, s, g, vm,
                            (const T *)st[0], (const T *)st[1], (const T *)st[2], (const T *)st[3],
-                           (const T *)st[4], part);
+                           (const T *)st[4], part, nblocks(g));
         hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(BLOCK), 0, s, (const double *)part, nb,
                            out);
         return hipGetLastError();
@@ -935,7 +959,7 @@ hipError_t launch_short_step(int prec, int layout, const Geom &g, const double *
     return dispatch<RunShort>(prec, layout, g.nz / SEG, g, vm, in, out, slow, dtau, s);
 }
 
-int mass_partials(const Geom &g) { return nblocks(g); }
+int mass_partials(const Geom &g) { return npartials(g); }
 
 hipError_t launch_mass(int prec, int layout, const Geom &g, const double *vm, const void *rp,
                        double *partials, double *out, hipStream_t s)

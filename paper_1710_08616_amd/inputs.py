@@ -275,9 +275,16 @@ def workload(name: str) -> State:
                 of 10 long steps with 4 short steps per stage, dt = 10 s.
     large       1024x1024x64, 16 bubbles (r in 2..8 km), 100 long steps, n = 6.
     large_sub   128x128x64 sub-run of the same generator (oracle-sized).
+    xl          2048x2048x64, the same generator with 16 bubbles, 30 long steps,
+                n = 6 (the layout-comparison domain; flat lower boundary).
     """
     if name == "small":
         return make_state(64, 64, 32, seed=1710, dt=10.0, n_short=4, n_long=10, name=name)
+    if name == "xl":
+        seed = 1714
+        bub = random_bubbles(seed, 16, 2048 * 2000.0, 2048 * 2000.0)
+        return make_state(2048, 2048, 64, seed=seed, bubbles=bub, dt=10.0, n_short=6,
+                          n_long=30, name=name)
     if name in ("large", "large_sub"):
         n = 1024 if name == "large" else 128
         seed = 1711

@@ -43,6 +43,7 @@ extern "C" {
 #endif
 
 typedef struct hv_grid *hv_grid_t;
+typedef struct hv_ens *hv_ens_t;
 
 enum {
     HV_OK = 0,
@@ -100,8 +101,12 @@ int hv_state_init(hv_grid_t g, const double *const fields[5], const double *rho_
 /* Enqueue n_long RK3 long steps of length dt (s) with n_short HEVI short
  * steps per stage (stage lengths dt/3, dt/2, dt; each stage restarts its
  * short steps from the state at the start of the long step).  After every
- * long step the total mass is summed in float64.  Asynchronous: faults and
- * non-finite mass surface at the next hv_state_read / hv_mass. */
+ * long step the total mass is summed in float64.  The launch sequence of a
+ * long step is recorded once per n_short as a hipGraph and replayed on a
+ * private stream ordered after, and joined back into, the grid's stream
+ * (while hv_trace is on, the kernels are launched directly instead).
+ * Asynchronous: faults and non-finite mass surface at the next
+ * hv_state_read / hv_mass. */
 int hv_step(hv_grid_t g, double dt, int32_t n_long, int32_t n_short);
 
 /* Copy one field back to the host in canonical float64 layout (the paper's
@@ -112,8 +117,8 @@ int hv_state_read(hv_grid_t g, int32_t field, double *host_out);
 /* Total mass sum (rho_ref + rho') dx dy dz and the diagnostic total energy
  * (kinetic + internal + potential) of the current state, in float64 with a
  * fixed summation order.  Either output pointer may be NULL.  Returns
- * HV_ERR_NONFINITE if the mass after any step so far is not finite.
- * Synchronises the stream. */
+ * HV_ERR_NONFINITE if the mass of the current state is not finite (a
+ * non-finite value anywhere propagates into it).  Synchronises the stream. */
 int hv_mass(hv_grid_t g, double *mass_out, double *energy_out);
 
 /* Kernel timing with HIP events on the grid's stream, a measurement aid.
@@ -127,6 +132,15 @@ enum { HV_K_SLOW_PREP = 0, HV_K_SLOW_FLUX = 1, HV_K_SHORT_STEP = 2, HV_K_MASS = 
 int hv_trace(hv_grid_t g, int32_t on);
 int hv_trace_read(hv_grid_t g, int32_t kind, double *ms_total, int64_t *launches);
 
+/* Autotune: time each kernel kind (slow prep, slow flux, short step) of the
+ * loaded state with every tile shape (16x1, 8x2, 4x4 columns of a 256-thread
+ * block) and keep the fastest; results are bitwise independent of the shape.
+ * The choice is appended to a plain-text cache ($HV_TUNE_CACHE, else
+ * $HOME/.cache/hevi/tune.txt) that later grids of the same kind start from.
+ * tile_x_out (may be NULL) receives the chosen x-extent of the three kinds.
+ * Synchronises the stream; does not change the state. */
+int hv_tune(hv_grid_t g, int32_t *tile_x_out);
+
 /* Release the handle (never the caller's workspace).  NULL is a no-op. */
 void hv_grid_destroy(hv_grid_t g);
 
@@ -134,6 +148,33 @@ void hv_grid_destroy(hv_grid_t g);
  * failure that had no valid handle).  Never NULL; valid until the next call
  * on the same handle. */
 const char *hv_last_error(hv_grid_t g);
+
+/* ---------------------------------------------------------------------------
+ * Batched ensemble: n independent domains of uneven sizes advanced together.
+ * Every member has its own description (same precision and layout for all),
+ * state, reference columns and long-step length; all members take the same
+ * n_short.  One long step of the whole ensemble is one launch per phase
+ * (slow sweep, each short step, the mass sum) covering the tiles of every
+ * member, recorded once as a hipGraph and replayed.  Workspace, stream and
+ * error conventions are those of the single grid above; member indices are
+ * 0..n-1 in the order of descs.
+ * ------------------------------------------------------------------------- */
+size_t hv_ens_workspace_bytes(int32_t n, const hv_grid_desc *descs);
+int hv_ens_create(int32_t n, const hv_grid_desc *descs, void *dev_workspace, size_t bytes,
+                  void *hip_stream, hv_ens_t *out);
+int hv_ens_state_init(hv_ens_t e, int32_t member, const double *const fields[5],
+                      const double *rho_ref, const double *rhotheta_ref, const double *p_ref);
+/* dt_per_member: n long-step lengths (s). */
+int hv_ens_step(hv_ens_t e, const double *dt_per_member, int32_t n_long, int32_t n_short);
+int hv_ens_state_read(hv_ens_t e, int32_t member, int32_t field, double *host_out);
+int hv_ens_mass(hv_ens_t e, int32_t member, double *mass_out, double *energy_out);
+/* As hv_tune, per group of members with equal nz (groups in increasing nz):
+ * tile_x_out receives 3 entries per group, *ngroups_out the group count. */
+int hv_ens_tune(hv_ens_t e, int32_t *tile_x_out, int32_t *ngroups_out);
+int hv_ens_trace(hv_ens_t e, int32_t on);
+int hv_ens_trace_read(hv_ens_t e, int32_t kind, double *ms_total, int64_t *launches);
+void hv_ens_destroy(hv_ens_t e);
+const char *hv_ens_last_error(hv_ens_t e);
 
 #ifdef __cplusplus
 }

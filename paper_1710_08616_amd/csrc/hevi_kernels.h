@@ -1,10 +1,16 @@
-// hevi_kernels.h -- host-side launchers of the HEVI step kernels (internal).
+// hevi_kernels.h -- device-side member table and the host launchers of the
+// HEVI step kernels (internal to the library).
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <cstddef>
 
 namespace hv {
+
+constexpr int kSeg = 16;               // lanes per column
+constexpr int kBlock = 256;            // threads per block
+constexpr int kColsPerBlock = kBlock / kSeg;
+constexpr int kMaxPartials = 1024;     // mass-sum partials per member
 
 // Per-level constant table (float64), entry f*nz + k.
 enum VmField {
@@ -22,41 +28,59 @@ enum VmField {
     VM_NFIELDS
 };
 
-struct Geom {
-    int nx, ny, nz;
-    double rdx, rdy;     // 1/dx, 1/dy
-    double beta;         // off-centring of the vertical coupling
+// One domain as every kernel sees it (device memory, one record per member).
+// roles[0] is the buffer holding the state at the start of a long step (and
+// the current state between steps); roles[1], roles[2] are the two running
+// buffers.  The rotate kernel updates roles at the end of each long step, so
+// one captured launch sequence serves every long step.
+struct MemberDev {
+    int nx, ny, nz, npart;       // npart: mass partials of this member
+    int roles[4];
+    double rdx, rdy, beta, dt;   // dt: long step of this member
+    const double *vm;
+    double *partials;
+    double *sums;                // [0] perturbation mass, [1] energy
+    void *st[3][5];              // rho', U, V, W, Theta' of the three buffers
+    void *slow[7];               // S_U, S_V, S_W, R_Theta, theta_s, P0_s, C_s
+    void *spec[3];               // u, v, w of the stage input
 };
 
+// One launch covering the blocks of a group of members (all with the same nz).
+struct Group {
+    const MemberDev *mem;   // device member table
+    const int *ids;         // device: member ids of the group (nm)
+    const int *prefix;      // device: prefix sums of the members' block counts (nm + 1)
+    int nm;                 // members in the group
+    int nblocks;            // blocks of the launch (= prefix[nm])
+    int ti_log2;            // tile = (1 << ti_log2) columns along x by 16 >> ti_log2 along y
+};
+
+// Blocks a member needs for a tile shape.
+inline int tiles_of(int nx, int ny, int ti_log2)
+{
+    const int ti = 1 << ti_log2, tj = kColsPerBlock >> ti_log2;
+    return ((nx + ti - 1) / ti) * ((ny + tj - 1) / tj);
+}
+inline int partials_of(int nx, int ny)
+{
+    const int t = tiles_of(nx, ny, 4);
+    return t < kMaxPartials ? t : kMaxPartials;
+}
+
 // prec: 0 float64, 1 float32, 2 float32 sweeps + float64 column solve.
-// layout: 0 i-fastest, 1 column-fastest.
-// Arrays are device pointers of the grid's storage type.
-
-// st = {rho', U, V, W, Theta'}; prep = {u, v, w, theta_s, P0_s, C_s}
-hipError_t launch_slow_prep(int prec, int layout, const Geom &g, const double *vm,
-                            const void *const st[5], void *const prep[6], hipStream_t s);
-
-// uvw = {U, V, W}; spec = {u, v, w, theta_s}; out = {S_U, S_V, S_W, R_Theta}
-hipError_t launch_slow_flux(int prec, int layout, const Geom &g, const double *vm,
-                            const void *const uvw[3], const void *const spec[4],
-                            void *const out[4], hipStream_t s);
-
-// in/out = {rho', U, V, W, Theta'} (distinct buffers);
-// slow = {S_U, S_V, S_W, R_Theta, theta_s, P0_s, C_s}
-hipError_t launch_short_step(int prec, int layout, const Geom &g, const double *vm,
-                             const void *const in[5], void *const out[5],
-                             const void *const slow[7], double dtau, hipStream_t s);
-
-// Number of float64 partials launch_mass writes (one per block).
-int mass_partials(const Geom &g);
-
-// partial[b] = sum of rho' * vol over block b's columns; then one block sums
-// the partials in order into *out (out[0] = perturbation mass).
-hipError_t launch_mass(int prec, int layout, const Geom &g, const double *vm, const void *rp,
-                       double *partials, double *out, hipStream_t s);
-
-// Diagnostic energy sum of the state st into *out (same two-level order).
-hipError_t launch_energy(int prec, int layout, const Geom &g, const double *vm,
-                         const void *const st[5], double *partials, double *out, hipStream_t s);
+// layout: 0 i-fastest, 1 column-fastest.  L = nz / 16.
+hipError_t launch_slow_prep(int prec, int layout, int L, const Group &gr, int stage, int n_short,
+                            hipStream_t s);
+hipError_t launch_slow_flux(int prec, int layout, int L, const Group &gr, int stage, int n_short,
+                            hipStream_t s);
+hipError_t launch_short_step(int prec, int layout, int L, const Group &gr, int stage, int sub,
+                             int n_short, hipStream_t s);
+// gr: prefix over the members' partial counts.  Sums the perturbation mass
+// (energy = false) or the total energy of the current state into sums.
+hipError_t launch_sums(int prec, int layout, int L, const Group &gr, bool energy, hipStream_t s);
+// After the last short step: make the long step's result the current state.
+hipError_t launch_rotate(MemberDev *mem, int n, int n_short, hipStream_t s);
+// Set the long-step length of member q.
+hipError_t launch_set_dt(MemberDev *mem, int q, double dt, hipStream_t s);
 
 }  // namespace hv

@@ -40,9 +40,8 @@
 namespace hv {
 namespace {
 
-constexpr int SEG = 16;            // lanes per column
-constexpr int BLOCK = 256;         // threads per block
-constexpr int CPB = BLOCK / SEG;   // columns per block
+constexpr int SEG = kSeg;
+constexpr int BLOCK = kBlock;
 
 constexpr double kGamma = 1.4;
 constexpr double kGrav = 9.80665;
@@ -52,10 +51,40 @@ using vec_t = T __attribute__((ext_vector_type(L)));
 
 __device__ __forceinline__ int wrapc(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-// Block b covers columns 16b .. 16b+15.  (Walking a contiguous eighth of the
-// domain per XCD instead was measured slower: consecutive blocks already put
-// the j-neighbour tiles, 64 blocks apart at nx = 1024, on the same XCD.)
-__device__ __forceinline__ int tile_of_block() { return (int)blockIdx.x; }
+// Block -> (member, tile) -> this segment's column.  A launch covers the
+// blocks of every member of a group; prefix[] holds the members' first
+// blocks.  A tile is (1 << ti_log2) columns along x by 16 >> ti_log2 along y.
+struct Where {
+    const MemberDev *m;
+    int i, j, t;
+    bool active;
+};
+__device__ __forceinline__ Where locate(const Group &gr)
+{
+    const int b = (int)blockIdx.x;
+    int lo = 0, hi = gr.nm;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (gr.prefix[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    Where w;
+    w.m = gr.mem + gr.ids[lo];
+    w.t = b - gr.prefix[lo];
+    const int ti = 1 << gr.ti_log2, tj = kColsPerBlock >> gr.ti_log2;
+    const int tiles_x = (w.m->nx + ti - 1) / ti;
+    const int c = (int)threadIdx.x / SEG;
+    w.i = (w.t % tiles_x) * ti + (c & (ti - 1));
+    w.j = (w.t / tiles_x) * tj + (c >> gr.ti_log2);
+    w.active = w.i < w.m->nx && w.j < w.m->ny;
+    return w;
+}
+
+// buffer roles: the stage input of stage s, and the source/target of short step q
+__device__ __forceinline__ int stage_input(const MemberDev *m, int s, int n)
+{
+    return s == 0 ? m->roles[0] : m->roles[1 + ((n - 1) & 1)];
+}
 
 // Storage orders of a 3D field with nz levels per column.
 struct KIJ {
@@ -78,11 +107,11 @@ struct Lane {
     int i, j, p, k0, nx, ny, nz;
     size_t kstride;
 
-    __device__ Lane(const Geom &g, int col)
+    __device__ Lane(int nx_, int ny_, int nz_, int i_, int j_)
     {
-        nx = g.nx; ny = g.ny; nz = g.nz;
-        i = col % nx;
-        j = col / nx;
+        nx = nx_; ny = ny_; nz = nz_;
+        i = i_;
+        j = j_;
         p = threadIdx.x % SEG;
         k0 = p * L;
         kstride = Lay::kContig ? 1 : (size_t)nx * ny;
@@ -197,15 +226,25 @@ __device__ __forceinline__ T kface(T qLL, T qL, T qR, T qRR, T m)
 // slow sweep, part 1: specific velocities, theta and stage coefficients
 // --------------------------------------------------------------------------
 template <typename T, class Lay, int L>
-__global__ __launch_bounds__(BLOCK) void k_slow_prep(
-    Geom g, const double *__restrict__ vm, const T *__restrict__ rp, const T *__restrict__ U,
-    const T *__restrict__ V, const T *__restrict__ W, const T *__restrict__ tp,
-    T *__restrict__ uo, T *__restrict__ vo, T *__restrict__ wo, T *__restrict__ tho,
-    T *__restrict__ P0o, T *__restrict__ Cso)
+__global__ __launch_bounds__(BLOCK) void k_slow_prep(Group gr, int stage, int n_short)
 {
-    const int col = tile_of_block() * CPB + threadIdx.x / SEG;
-    if (col >= g.nx * g.ny) return;
-    const Lane<Lay, L> ln(g, col);
+    const Where wh = locate(gr);
+    if (!wh.active) return;
+    const MemberDev *m = wh.m;
+    const Lane<Lay, L> ln(m->nx, m->ny, m->nz, wh.i, wh.j);
+    const double *__restrict__ vm = m->vm;
+    void *const *in = m->st[stage_input(m, stage, n_short)];
+    const T *__restrict__ rp = (const T *)in[0];
+    const T *__restrict__ U = (const T *)in[1];
+    const T *__restrict__ V = (const T *)in[2];
+    const T *__restrict__ W = (const T *)in[3];
+    const T *__restrict__ tp = (const T *)in[4];
+    T *__restrict__ uo = (T *)m->spec[0];
+    T *__restrict__ vo = (T *)m->spec[1];
+    T *__restrict__ wo = (T *)m->spec[2];
+    T *__restrict__ tho = (T *)m->slow[4];
+    T *__restrict__ P0o = (T *)m->slow[5];
+    T *__restrict__ Cso = (T *)m->slow[6];
 
     T r0[L], rw[L], rs[L], Uc[L], Vc[L], Wc[L], tc[L];
     ln.load(rp, 0, 0, r0);
@@ -481,16 +520,26 @@ __device__ __forceinline__ void slow_rt(const Lane<Lay, L> &ln, T rdx, T rdy, co
 }
 
 template <typename T, class Lay, int L>
-__global__ __launch_bounds__(BLOCK) void k_slow_flux(
-    Geom g, const double *__restrict__ vm, const T *__restrict__ U, const T *__restrict__ V,
-    const T *__restrict__ W, const T *__restrict__ uu, const T *__restrict__ vv,
-    const T *__restrict__ ww, const T *__restrict__ th, T *__restrict__ SU, T *__restrict__ SV,
-    T *__restrict__ SW, T *__restrict__ RT)
+__global__ __launch_bounds__(BLOCK) void k_slow_flux(Group gr, int stage, int n_short)
 {
-    const int col = tile_of_block() * CPB + threadIdx.x / SEG;
-    if (col >= g.nx * g.ny) return;
-    const Lane<Lay, L> ln(g, col);
-    const T rdx = (T)g.rdx, rdy = (T)g.rdy;
+    const Where wh = locate(gr);
+    if (!wh.active) return;
+    const MemberDev *m = wh.m;
+    const Lane<Lay, L> ln(m->nx, m->ny, m->nz, wh.i, wh.j);
+    const double *__restrict__ vm = m->vm;
+    void *const *in = m->st[stage_input(m, stage, n_short)];
+    const T *__restrict__ U = (const T *)in[1];
+    const T *__restrict__ V = (const T *)in[2];
+    const T *__restrict__ W = (const T *)in[3];
+    const T *__restrict__ uu = (const T *)m->spec[0];
+    const T *__restrict__ vv = (const T *)m->spec[1];
+    const T *__restrict__ ww = (const T *)m->spec[2];
+    const T *__restrict__ th = (const T *)m->slow[4];
+    T *__restrict__ SU = (T *)m->slow[0];
+    T *__restrict__ SV = (T *)m->slow[1];
+    T *__restrict__ SW = (T *)m->slow[2];
+    T *__restrict__ RT = (T *)m->slow[3];
+    const T rdx = (T)m->rdx, rdy = (T)m->rdy;
     T rdz[L];
     ln.vmet(vm, VM_RDZ, rdz);
     slow_su(ln, rdx, rdy, rdz, U, V, W, uu, SU);
@@ -571,18 +620,37 @@ __device__ __forceinline__ void segment_solve(int p, const S (&A)[L], const S (&
 }
 
 template <typename T, typename S, class Lay, int L>
-__global__ __launch_bounds__(BLOCK) void k_short_step(
-    Geom g, const double *__restrict__ vm, double dtau_d, const T *__restrict__ rp,
-    const T *__restrict__ U, const T *__restrict__ V, const T *__restrict__ W,
-    const T *__restrict__ tp, T *__restrict__ rpo, T *__restrict__ Uo, T *__restrict__ Vo,
-    T *__restrict__ Wo, T *__restrict__ tpo, const T *__restrict__ SU,
-    const T *__restrict__ SV, const T *__restrict__ SW, const T *__restrict__ RT,
-    const T *__restrict__ ths, const T *__restrict__ P0, const T *__restrict__ Cs)
+__global__ __launch_bounds__(BLOCK) void k_short_step(Group gr, int stage, int sub, int n_short)
 {
-    const int col = tile_of_block() * CPB + threadIdx.x / SEG;
-    if (col >= g.nx * g.ny) return;
-    const Lane<Lay, L> ln(g, col);
-    const T dt = (T)dtau_d, rdx = (T)g.rdx, rdy = (T)g.rdy;
+    const Where wh = locate(gr);
+    if (!wh.active) return;
+    const MemberDev *m = wh.m;
+    const Lane<Lay, L> ln(m->nx, m->ny, m->nz, wh.i, wh.j);
+    const double *__restrict__ vm = m->vm;
+    const int src = sub == 0 ? m->roles[0] : m->roles[1 + ((sub - 1) & 1)];
+    const int dst = m->roles[1 + (sub & 1)];
+    void *const *in = m->st[src];
+    void *const *out = m->st[dst];
+    const T *__restrict__ rp = (const T *)in[0];
+    const T *__restrict__ U = (const T *)in[1];
+    const T *__restrict__ V = (const T *)in[2];
+    const T *__restrict__ W = (const T *)in[3];
+    const T *__restrict__ tp = (const T *)in[4];
+    T *__restrict__ rpo = (T *)out[0];
+    T *__restrict__ Uo = (T *)out[1];
+    T *__restrict__ Vo = (T *)out[2];
+    T *__restrict__ Wo = (T *)out[3];
+    T *__restrict__ tpo = (T *)out[4];
+    const T *__restrict__ SU = (const T *)m->slow[0];
+    const T *__restrict__ SV = (const T *)m->slow[1];
+    const T *__restrict__ SW = (const T *)m->slow[2];
+    const T *__restrict__ RT = (const T *)m->slow[3];
+    const T *__restrict__ ths = (const T *)m->slow[4];
+    const T *__restrict__ P0 = (const T *)m->slow[5];
+    const T *__restrict__ Cs = (const T *)m->slow[6];
+    const double frac = stage == 0 ? 1.0 / 3.0 : (stage == 1 ? 0.5 : 1.0);
+    const double dtau_d = m->dt * frac / n_short;
+    const T dt = (T)dtau_d, rdx = (T)m->rdx, rdy = (T)m->rdy;
 
     // ---- horizontally explicit part (storage precision) ----
     T pc[L], pw[L], pe[L], ps[L], pn[L];
@@ -648,7 +716,7 @@ __global__ __launch_bounds__(BLOCK) void k_short_step(
     ln.store(Vo, Vp);
 
     // ---- vertically implicit part (solve precision S) ----
-    const S be = (S)g.beta, dts = (S)dtau_d;
+    const S be = (S)m->beta, dts = (S)dtau_d;
     const S one_m_be = S(1) - be;
     const S mu = be * be * dts * dts;
     const S grav = (S)kGrav;
@@ -750,99 +818,112 @@ __device__ __forceinline__ double block_sum(double v, double *sh)
     return sh[0];
 }
 
-// Partial sums: block b accumulates the tiles b, b + G, b + 2G, ... (G = grid
-// size, fixed by the domain) in that order, each lane in float64, then a fixed
-// tree over the block.
-template <typename T, class Lay, int L>
-__global__ __launch_bounds__(BLOCK) void k_mass_partial(Geom g, const double *__restrict__ vm,
-                                                        const T *__restrict__ rp,
-                                                        double *__restrict__ part, int ntiles)
+// Partial sums of one member: its partial block q accumulates the member's
+// 16x1 tiles q, q + P, q + 2P, ... (P = its partial count) in that order, each
+// lane in float64, then a fixed tree over the block.  The launch covers the
+// partial blocks of every member of a group (gr.prefix over partial counts).
+template <typename T, class Lay, int L, bool ENERGY>
+__global__ __launch_bounds__(BLOCK) void k_sum_partial(Group gr)
 {
     __shared__ double sh[BLOCK];
-    double vol[L];
-    double acc = 0.0;
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const int col = t * CPB + threadIdx.x / SEG;
-        if (col < g.nx * g.ny) {
-            const Lane<Lay, L> ln(g, col);
-            ln.vmet(vm, VM_VOL, vol);
-            T r[L];
-            ln.template load<true>(rp, 0, 0, r);
-#pragma unroll
-            for (int l = 0; l < L; ++l) acc += (double)r[l] * vol[l];
-        }
+    const int b = (int)blockIdx.x;
+    int lo = 0, hi = gr.nm;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (gr.prefix[mid] <= b) lo = mid;
+        else hi = mid;
     }
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
-}
-
-template <typename T, class Lay, int L>
-__global__ __launch_bounds__(BLOCK) void k_energy_partial(
-    Geom g, const double *__restrict__ vm, const T *__restrict__ rp, const T *__restrict__ U,
-    const T *__restrict__ V, const T *__restrict__ W, const T *__restrict__ tp,
-    double *__restrict__ part, int ntiles)
-{
-    __shared__ double sh[BLOCK];
+    const MemberDev *m = gr.mem + gr.ids[lo];
+    const int q = b - gr.prefix[lo];
+    const int tiles_x = (m->nx + kColsPerBlock - 1) / kColsPerBlock;
+    const int ntiles = tiles_x * m->ny;
+    const double *__restrict__ vm = m->vm;
+    void *const *st = m->st[m->roles[0]];
     double acc = 0.0;
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const int col = t * CPB + threadIdx.x / SEG;
-        if (col < g.nx * g.ny) {
-            const Lane<Lay, L> ln(g, col);
-            T r[L], u0[L], u1[L], v0[L], v1[L], w0[L], th[L];
-            ln.load(rp, 0, 0, r);
-            ln.load(U, 0, 0, u0);
-            ln.load(U, 1, 0, u1);
-            ln.load(V, 0, 0, v0);
-            ln.load(V, 0, 1, v1);
-            ln.load(W, 0, 0, w0);
-            ln.load(tp, 0, 0, th);
-            const T wt = from_above(w0[0]);
-            double vol[L], rref[L], rtref[L], pref[L], zc[L];
+    for (int t = q; t < ntiles; t += m->npart) {
+        const int i = (t % tiles_x) * kColsPerBlock + (int)threadIdx.x / SEG;
+        const int j = t / tiles_x;
+        if (i < m->nx) {
+            const Lane<Lay, L> ln(m->nx, m->ny, m->nz, i, j);
+            double vol[L];
             ln.vmet(vm, VM_VOL, vol);
-            ln.vmet(vm, VM_RHO, rref);
-            ln.vmet(vm, VM_RT, rtref);
-            ln.vmet(vm, VM_P, pref);
-            ln.vmet(vm, VM_ZC, zc);
+            if constexpr (!ENERGY) {
+                T r[L];
+                ln.template load<true>((const T *)st[0], 0, 0, r);
 #pragma unroll
-            for (int l = 0; l < L; ++l) {
-                const double rho = rref[l] + (double)r[l];
-                const double wu = (l < L - 1) ? (double)w0[l + 1] : (ln.p == SEG - 1 ? 0.0 : (double)wt);
-                const double a = (double)u0[l], b = (double)u1[l], c = (double)v0[l], d = (double)v1[l];
-                const double e = (double)w0[l];
-                const double ke = 0.5 * (0.5 * (a * a + b * b) + 0.5 * (c * c + d * d) + 0.5 * (e * e + wu * wu)) / rho;
-                const double pres = pref[l] + pref[l] * expm1(kGamma * log1p((double)th[l] / rtref[l]));
-                acc += (ke + pres / (kGamma - 1.0) + rho * kGrav * zc[l]) * vol[l];
+                for (int l = 0; l < L; ++l) acc += (double)r[l] * vol[l];
+            } else {
+                T r[L], u0[L], u1[L], v0[L], v1[L], w0[L], th[L];
+                ln.load((const T *)st[0], 0, 0, r);
+                ln.load((const T *)st[1], 0, 0, u0);
+                ln.load((const T *)st[1], 1, 0, u1);
+                ln.load((const T *)st[2], 0, 0, v0);
+                ln.load((const T *)st[2], 0, 1, v1);
+                ln.load((const T *)st[3], 0, 0, w0);
+                ln.load((const T *)st[4], 0, 0, th);
+                const T wt = from_above(w0[0]);
+                double rref[L], rtref[L], pref[L], zc[L];
+                ln.vmet(vm, VM_RHO, rref);
+                ln.vmet(vm, VM_RT, rtref);
+                ln.vmet(vm, VM_P, pref);
+                ln.vmet(vm, VM_ZC, zc);
+#pragma unroll
+                for (int l = 0; l < L; ++l) {
+                    const double rho = rref[l] + (double)r[l];
+                    const double wu = (l < L - 1) ? (double)w0[l + 1] : (ln.p == SEG - 1 ? 0.0 : (double)wt);
+                    const double a = (double)u0[l], bb = (double)u1[l], c = (double)v0[l];
+                    const double d = (double)v1[l], e = (double)w0[l];
+                    const double ke = 0.5 * (0.5 * (a * a + bb * bb) + 0.5 * (c * c + d * d) +
+                                             0.5 * (e * e + wu * wu)) / rho;
+                    const double pres = pref[l] + pref[l] * expm1(kGamma * log1p((double)th[l] / rtref[l]));
+                    acc += (ke + pres / (kGamma - 1.0) + rho * kGrav * zc[l]) * vol[l];
+                }
             }
         }
     }
     const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    if (threadIdx.x == 0) m->partials[q] = s;
 }
 
-// Sum n partials in a fixed order: thread t takes t, t+BLOCK, ... with a
-// Neumaier-compensated running sum, then a fixed tree over the block.
-__global__ __launch_bounds__(BLOCK) void k_sum_partials(const double *__restrict__ part, int n,
-                                                        double *__restrict__ out)
+// One block per member of the group: sum its partials in a fixed order
+// (thread t takes t, t + BLOCK, ... with Neumaier compensation, then a tree).
+__global__ __launch_bounds__(BLOCK) void k_sum_final(Group gr, int slot)
 {
     __shared__ double sh[BLOCK];
+    const MemberDev *m = gr.mem + gr.ids[blockIdx.x];
     double s = 0.0, c = 0.0;
-    for (int q = threadIdx.x; q < n; q += BLOCK) {
-        const double x = part[q];
+    for (int q = threadIdx.x; q < m->npart; q += BLOCK) {
+        const double x = m->partials[q];
         const double t = s + x;
         c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
         s = t;
     }
     const double tot = block_sum(s + c, sh);
-    if (threadIdx.x == 0) out[0] = tot;
+    if (threadIdx.x == 0) m->sums[slot] = tot;
+}
+
+__global__ void k_set_dt(MemberDev *mem, int q, double dt)
+{
+    if (threadIdx.x == 0) mem[q].dt = dt;
+}
+
+// The long step's result (written by the last short step of stage 3) becomes
+// the start buffer of the next long step.
+__global__ void k_rotate(MemberDev *mem, int n, int n_short)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    MemberDev *m = mem + q;
+    const int cur = m->roles[1 + ((n_short - 1) & 1)];
+    const int a = m->roles[0], b = m->roles[1 + (n_short & 1)];
+    m->roles[0] = cur;
+    m->roles[1] = a;
+    m->roles[2] = b;
 }
 
 // --------------------------------------------------------------------------
 // dispatch
 // --------------------------------------------------------------------------
-inline int nblocks(const Geom &g) { return (g.nx * g.ny + CPB - 1) / CPB; }
-constexpr int kMaxPartials = 1024;
-inline int npartials(const Geom &g) { return nblocks(g) < kMaxPartials ? nblocks(g) : kMaxPartials; }
-
 template <template <typename, typename, class, int> class F, typename... Args>
 hipError_t dispatch(int prec, int layout, int L, Args &&...args)
 {
@@ -869,108 +950,82 @@ hipError_t dispatch(int prec, int layout, int L, Args &&...args)
 
 template <typename T, typename S, class Lay, int L>
 struct RunPrep {
-    static hipError_t run(const Geom &g, const double *vm, const void *const *st,
-                          void *const *pr, hipStream_t s)
+    static hipError_t run(const Group &gr, int stage, int n_short, hipStream_t s)
     {
-        hipLaunchKernelGGL((k_slow_prep<T, Lay, L>), dim3(nblocks(g)), dim3(BLOCK), 0, s, g, vm,
-                           (const T *)st[0], (const T *)st[1], (const T *)st[2], (const T *)st[3],
-                           (const T *)st[4], (T *)pr[0], (T *)pr[1], (T *)pr[2], (T *)pr[3],
-                           (T *)pr[4], (T *)pr[5]);
+        hipLaunchKernelGGL((k_slow_prep<T, Lay, L>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr, stage,
+                           n_short);
         return hipGetLastError();
     }
 };
 
 template <typename T, typename S, class Lay, int L>
 struct RunFlux {
-    static hipError_t run(const Geom &g, const double *vm, const void *const *uvw,
-                          const void *const *sp, void *const *out, hipStream_t s)
+    static hipError_t run(const Group &gr, int stage, int n_short, hipStream_t s)
     {
-        hipLaunchKernelGGL((k_slow_flux<T, Lay, L>), dim3(nblocks(g)), dim3(BLOCK), 0, s, g, vm,
-                           (const T *)uvw[0], (const T *)uvw[1], (const T *)uvw[2],
-                           (const T *)sp[0], (const T *)sp[1], (const T *)sp[2], (const T *)sp[3],
-                           (T *)out[0], (T *)out[1], (T *)out[2], (T *)out[3]);
+        hipLaunchKernelGGL((k_slow_flux<T, Lay, L>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr, stage,
+                           n_short);
         return hipGetLastError();
     }
 };
 
 template <typename T, typename S, class Lay, int L>
 struct RunShort {
-    static hipError_t run(const Geom &g, const double *vm, const void *const *in, void *const *out,
-                          const void *const *sl, double dtau, hipStream_t s)
+    static hipError_t run(const Group &gr, int stage, int sub, int n_short, hipStream_t s)
     {
-        hipLaunchKernelGGL((k_short_step<T, S, Lay, L>), dim3(nblocks(g)), dim3(BLOCK), 0, s, g,
-                           vm, dtau, (const T *)in[0], (const T *)in[1], (const T *)in[2],
-                           (const T *)in[3], (const T *)in[4], (T *)out[0], (T *)out[1],
-                           (T *)out[2], (T *)out[3], (T *)out[4], (const T *)sl[0],
-                           (const T *)sl[1], (const T *)sl[2], (const T *)sl[3], (const T *)sl[4],
-                           (const T *)sl[5], (const T *)sl[6]);
+        hipLaunchKernelGGL((k_short_step<T, S, Lay, L>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr,
+                           stage, sub, n_short);
         return hipGetLastError();
     }
 };
 
 template <typename T, typename S, class Lay, int L>
-struct RunMass {
-    static hipError_t run(const Geom &g, const double *vm, const void *rp, double *part,
-                          double *out, hipStream_t s)
+struct RunSums {
+    static hipError_t run(const Group &gr, bool energy, hipStream_t s)
     {
-        const int nb = npartials(g);
-        hipLaunchKernelGGL((k_mass_partial<T, Lay, L>), dim3(nb), dim3(BLOCK), 0, s, g, vm,
-                           (const T *)rp, part, nblocks(g));
-        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(BLOCK), 0, s, (const double *)part, nb,
-                           out);
-        return hipGetLastError();
-    }
-};
-
-template <typename T, typename S, class Lay, int L>
-struct RunEnergy {
-    static hipError_t run(const Geom &g, const double *vm, const void *const *st, double *part,
-                          double *out, hipStream_t s)
-    {
-        const int nb = npartials(g);
-        hipLaunchKernelGGL((k_energy_partial<T, Lay, L>), dim3(nb), dim3(BLOCK), 0, s, g, vm,
-                           (const T *)st[0], (const T *)st[1], (const T *)st[2], (const T *)st[3],
-                           (const T *)st[4], part, nblocks(g));
-        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(BLOCK), 0, s, (const double *)part, nb,
-                           out);
+        if (energy)
+            hipLaunchKernelGGL((k_sum_partial<T, Lay, L, true>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr);
+        else
+            hipLaunchKernelGGL((k_sum_partial<T, Lay, L, false>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr);
+        hipLaunchKernelGGL(k_sum_final, dim3(gr.nm), dim3(BLOCK), 0, s, gr, energy ? 1 : 0);
         return hipGetLastError();
     }
 };
 
 }  // namespace
 
-hipError_t launch_slow_prep(int prec, int layout, const Geom &g, const double *vm,
-                            const void *const st[5], void *const prep[6], hipStream_t s)
+hipError_t launch_slow_prep(int prec, int layout, int L, const Group &gr, int stage, int n_short,
+                            hipStream_t s)
 {
-    return dispatch<RunPrep>(prec, layout, g.nz / SEG, g, vm, st, prep, s);
+    return dispatch<RunPrep>(prec, layout, L, gr, stage, n_short, s);
 }
 
-hipError_t launch_slow_flux(int prec, int layout, const Geom &g, const double *vm,
-                            const void *const uvw[3], const void *const spec[4],
-                            void *const out[4], hipStream_t s)
+hipError_t launch_slow_flux(int prec, int layout, int L, const Group &gr, int stage, int n_short,
+                            hipStream_t s)
 {
-    return dispatch<RunFlux>(prec, layout, g.nz / SEG, g, vm, uvw, spec, out, s);
+    return dispatch<RunFlux>(prec, layout, L, gr, stage, n_short, s);
 }
 
-hipError_t launch_short_step(int prec, int layout, const Geom &g, const double *vm,
-                             const void *const in[5], void *const out[5],
-                             const void *const slow[7], double dtau, hipStream_t s)
+hipError_t launch_short_step(int prec, int layout, int L, const Group &gr, int stage, int sub,
+                             int n_short, hipStream_t s)
 {
-    return dispatch<RunShort>(prec, layout, g.nz / SEG, g, vm, in, out, slow, dtau, s);
+    return dispatch<RunShort>(prec, layout, L, gr, stage, sub, n_short, s);
 }
 
-int mass_partials(const Geom &g) { return npartials(g); }
-
-hipError_t launch_mass(int prec, int layout, const Geom &g, const double *vm, const void *rp,
-                       double *partials, double *out, hipStream_t s)
+hipError_t launch_sums(int prec, int layout, int L, const Group &gr, bool energy, hipStream_t s)
 {
-    return dispatch<RunMass>(prec, layout, g.nz / SEG, g, vm, rp, partials, out, s);
+    return dispatch<RunSums>(prec, layout, L, gr, energy, s);
 }
 
-hipError_t launch_energy(int prec, int layout, const Geom &g, const double *vm,
-                         const void *const st[5], double *partials, double *out, hipStream_t s)
+hipError_t launch_set_dt(MemberDev *mem, int q, double dt, hipStream_t s)
 {
-    return dispatch<RunEnergy>(prec, layout, g.nz / SEG, g, vm, st, partials, out, s);
+    hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(64), 0, s, mem, q, dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_rotate(MemberDev *mem, int n, int n_short, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rotate, dim3((n + 63) / 64), dim3(64), 0, s, mem, n, n_short);
+    return hipGetLastError();
 }
 
 }  // namespace hv

@@ -1,14 +1,28 @@
-// hevi_runtime.cpp -- host runtime behind the C ABI declared in include/hevi.h:
-// workspace carving, state copy-in/out with layout and precision conversion,
-// and the RK3 / short-step launch sequence.
+// hevi_runtime.cpp -- host runtime behind the C ABI declared in include/hevi.h.
+//
+// A grid is an ensemble of one member.  An ensemble keeps, inside the
+// caller's workspace, a device table with one record per member (sizes,
+// spacings, long-step length, buffer roles and array pointers) and, per group
+// of members with the same nz, the member ids and block prefix sums each
+// grouped launch uses.  One long step is the launch sequence
+//   for each stage: slow prep, slow flux, n short steps   (per group)
+//   rotate buffer roles                                    (all members)
+//   mass partials + final sums                             (per group)
+// recorded once into a hipGraph on a private stream and replayed n_long times;
+// with tracing on, the same sequence is launched directly with an event pair
+// around each launch.
 #include "hevi.h"
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -17,39 +31,50 @@
 namespace {
 
 thread_local std::string g_global_error = "no error";
-
 constexpr size_t kAlign = 256;
-constexpr int kSeg = 16;
-
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// tile shapes the autotuner tries: log2 of the columns along x (16x1, 8x2, 4x4)
+constexpr int kShapes[3] = {4, 3, 2};
+enum { KIND_PREP = 0, KIND_FLUX = 1, KIND_SHORT = 2, NKIND = 3 };
+
+struct MemberHost {
+    int nx = 0, ny = 0, nz = 0, L = 0;
+    double dx = 0, dy = 0, beta = 0.55, dt = -1.0;
+    std::vector<double> zf;
+    size_t ncell = 0;
+    hv::MemberDev dev{};       // host copy of the device record
+    int roles[3] = {0, 1, 2};  // host mirror of dev.roles
+    double mass_ref = 0.0;
+    bool have_state = false;
+};
+
+struct GroupHost {
+    int L = 0;
+    std::vector<int> ids;
+    int *d_ids = nullptr;
+    int *d_prefix[3] = {};     // block prefix per tile shape
+    int *d_pprefix = nullptr;  // prefix of partial counts
+    int nblocks[3] = {};
+    int npblocks = 0;
+    int shape[NKIND] = {0, 0, 0};  // index into kShapes per kernel kind
+};
 
 }  // namespace
 
-struct hv_grid {
-    int nx = 0, ny = 0, nz = 0;
-    double dx = 0, dy = 0, beta = 0.55;
-    int prec = 0, layout = 1;
-    size_t esize = 8;            // bytes per stored value
-    size_t ncell = 0;            // nx*ny*nz
-    hipStream_t stream = nullptr;
-    std::vector<double> zf;
-    hv::Geom geom{};
-
-    // device arrays carved from the caller's workspace
-    void *state[3][5] = {};      // three state buffers
-    int cur = 0;                 // index of the buffer holding the current state
-    void *slow[7] = {};          // S_U, S_V, S_W, R_Theta, theta_s, P0_s, C_s
-    void *spec[3] = {};          // u, v, w of the stage input
-    double *vm = nullptr;        // per-level constants
-    double *partials = nullptr;  // per-block sums
-    double *sums = nullptr;      // [0] perturbation mass after the last step,
-                                 // [1] scratch, [2] nonfinite flag (max |.|)
-    double mass_ref = 0.0;       // sum of rho_ref * volume (constant part)
-    bool have_state = false;
-    bool any_nonfinite = false;
+struct hv_ens {
+    int n = 0, prec = 0, layout = 1;
+    size_t esize = 8;
+    hipStream_t stream = nullptr;    // caller's stream
+    hipStream_t own = nullptr;       // private stream for graph replay
+    hipEvent_t fork = nullptr, join = nullptr;
+    std::vector<MemberHost> m;
+    std::vector<GroupHost> groups;
+    hv::MemberDev *d_mem = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_nshort = -1;
     std::string err = "no error";
 
-    // kernel timing (hv_trace)
     struct Pending { int kind; hipEvent_t a, b; };
     bool tracing = false;
     std::vector<Pending> pending;
@@ -57,29 +82,33 @@ struct hv_grid {
     double trace_ms[HV_K_COUNT] = {};
     int64_t trace_n[HV_K_COUNT] = {};
 
-    ~hv_grid()
+    ~hv_ens()
     {
+        if (exec) (void)hipGraphExecDestroy(exec);
         for (auto &p : pending) { pool.push_back(p.a); pool.push_back(p.b); }
         for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+        if (own) (void)hipStreamDestroy(own);
     }
 };
 
+struct hv_grid : hv_ens {};
+
 namespace {
 
-int fail(hv_grid *g, int code, const std::string &msg)
+int fail(hv_ens *e, int code, const std::string &msg)
 {
-    if (g) g->err = msg;
+    if (e) e->err = msg;
     else g_global_error = msg;
     return code;
 }
 
-int hip_fail(hv_grid *g, hipError_t e, const char *what)
+int hip_fail(hv_ens *e, hipError_t err, const char *what)
 {
-    std::string m = std::string(what) + ": " + hipGetErrorString(e);
-    return fail(g, HV_ERR_HIP, m);
+    return fail(e, HV_ERR_HIP, std::string(what) + ": " + hipGetErrorString(err));
 }
 
-// Validate a description; returns an empty string if it is usable.
 std::string check_desc(const hv_grid_desc *d)
 {
     if (!d) return "desc is NULL";
@@ -118,74 +147,96 @@ struct Carve {
     }
 };
 
-// Layout of the workspace; returns the total size.
-size_t plan(const hv_grid_desc *d, size_t *offs /* 3*5 + 7 + 3 + 3 */)
-{
-    const size_t n = (size_t)d->nx * d->ny * d->nz;
-    const size_t es = elem_size(d->precision);
-    hv::Geom g{d->nx, d->ny, d->nz, 0, 0, 0};
-    Carve c;
-    int q = 0;
-    for (int b = 0; b < 3; ++b)
-        for (int f = 0; f < 5; ++f) offs[q++] = c.take(n * es);
-    for (int f = 0; f < 7; ++f) offs[q++] = c.take(n * es);
-    for (int f = 0; f < 3; ++f) offs[q++] = c.take(n * es);
-    offs[q++] = c.take(sizeof(double) * hv::VM_NFIELDS * d->nz);
-    offs[q++] = c.take(sizeof(double) * (size_t)hv::mass_partials(g));
-    offs[q++] = c.take(sizeof(double) * 4);
-    return c.off;
-}
-constexpr int kNOffs = 15 + 7 + 3 + 3;
+// Workspace plan of an ensemble.  With base == nullptr only sizes are computed.
+struct Plan {
+    size_t total = 0;
+    size_t table = 0;
+    std::vector<size_t> group_off;  // per group: ids, 3 prefixes, partial prefix
+    std::vector<size_t> member_off; // per member: 25 arrays, vm, partials, sums
+};
 
-// canonical (i-fastest, float64) index of cell (i, j, k)
+std::vector<std::vector<int>> group_members(int n, const hv_grid_desc *d)
+{
+    std::vector<std::vector<int>> g;
+    for (int nz : {32, 64, 128}) {
+        std::vector<int> ids;
+        for (int q = 0; q < n; ++q)
+            if (d[q].nz == nz) ids.push_back(q);
+        if (!ids.empty()) g.push_back(ids);
+    }
+    return g;
+}
+
+Plan make_plan(int n, const hv_grid_desc *d)
+{
+    Plan p;
+    Carve c;
+    p.table = c.take(sizeof(hv::MemberDev) * (size_t)n);
+    for (auto &ids : group_members(n, d)) {
+        const size_t nm = ids.size();
+        p.group_off.push_back(c.take(sizeof(int) * (nm + 4 * (nm + 1))));
+    }
+    const size_t es = elem_size(d[0].precision);
+    for (int q = 0; q < n; ++q) {
+        const size_t ncell = (size_t)d[q].nx * d[q].ny * d[q].nz;
+        const size_t start = c.take(0);
+        for (int a = 0; a < 25; ++a) c.take(ncell * es);
+        c.take(sizeof(double) * hv::VM_NFIELDS * d[q].nz);
+        c.take(sizeof(double) * (size_t)hv::partials_of(d[q].nx, d[q].ny));
+        c.take(sizeof(double) * 4);
+        p.member_off.push_back(start);
+    }
+    p.total = c.off;
+    return p;
+}
+
 inline size_t canon(int i, int j, int k, int nx, int ny) { return ((size_t)k * ny + j) * nx + i; }
 
-inline size_t dev_index(const hv_grid *g, int i, int j, int k)
+inline size_t dev_index(int layout, const MemberHost &m, int i, int j, int k)
 {
-    if (g->layout == HV_KIJ) return ((size_t)j * g->nx + i) * g->nz + k;
-    return ((size_t)k * g->ny + j) * g->nx + i;
+    if (layout == HV_KIJ) return ((size_t)j * m.nx + i) * m.nz + k;
+    return ((size_t)k * m.ny + j) * m.nx + i;
 }
 
 template <typename T>
-void to_device_order(const hv_grid *g, const double *src, T *dst)
+void to_device_order(int layout, const MemberHost &m, const double *src, T *dst)
 {
-    for (int k = 0; k < g->nz; ++k)
-        for (int j = 0; j < g->ny; ++j)
-            for (int i = 0; i < g->nx; ++i)
-                dst[dev_index(g, i, j, k)] = (T)src[canon(i, j, k, g->nx, g->ny)];
+    for (int k = 0; k < m.nz; ++k)
+        for (int j = 0; j < m.ny; ++j)
+            for (int i = 0; i < m.nx; ++i)
+                dst[dev_index(layout, m, i, j, k)] = (T)src[canon(i, j, k, m.nx, m.ny)];
 }
 
 template <typename T>
-void from_device_order(const hv_grid *g, const T *src, double *dst)
+void from_device_order(int layout, const MemberHost &m, const T *src, double *dst)
 {
-    for (int k = 0; k < g->nz; ++k)
-        for (int j = 0; j < g->ny; ++j)
-            for (int i = 0; i < g->nx; ++i)
-                dst[canon(i, j, k, g->nx, g->ny)] = (double)src[dev_index(g, i, j, k)];
+    for (int k = 0; k < m.nz; ++k)
+        for (int j = 0; j < m.ny; ++j)
+            for (int i = 0; i < m.nx; ++i)
+                dst[canon(i, j, k, m.nx, m.ny)] = (double)src[dev_index(layout, m, i, j, k)];
 }
 
-void fill_vmet(hv_grid *g, const double *rho, const double *rt, const double *p, std::vector<double> &vm)
+void fill_vmet(const MemberHost &m, const double *rho, const double *rt, const double *p,
+               std::vector<double> &vm)
 {
-    const int nz = g->nz;
+    const int nz = m.nz;
     vm.assign((size_t)hv::VM_NFIELDS * nz, 0.0);
     auto at = [&](int f, int k) -> double & { return vm[(size_t)f * nz + k]; };
     for (int k = 0; k < nz; ++k) {
-        const double dz = g->zf[k + 1] - g->zf[k];
+        const double dz = m.zf[k + 1] - m.zf[k];
         at(hv::VM_DZ, k) = dz;
         at(hv::VM_RDZ, k) = 1.0 / dz;
-        at(hv::VM_VOL, k) = g->dx * g->dy * dz;
-        at(hv::VM_ZC, k) = 0.5 * (g->zf[k + 1] + g->zf[k]);
-        at(hv::VM_RHO, k) = rho ? rho[k] : 0.0;
-        at(hv::VM_RT, k) = rt ? rt[k] : 1.0;
-        at(hv::VM_P, k) = p ? p[k] : 0.0;
+        at(hv::VM_VOL, k) = m.dx * m.dy * dz;
+        at(hv::VM_ZC, k) = 0.5 * (m.zf[k + 1] + m.zf[k]);
+        at(hv::VM_RHO, k) = rho[k];
+        at(hv::VM_RT, k) = rt[k];
+        at(hv::VM_P, k) = p[k];
         if (k == 0) {
             at(hv::VM_DZF, k) = 1.0;
             at(hv::VM_RDZF, k) = 1.0;
-            at(hv::VM_A, k) = 0.0;
-            at(hv::VM_B, k) = 0.0;
         } else {
-            const double dzm = g->zf[k] - g->zf[k - 1];
-            const double dzf = 0.5 * (g->zf[k + 1] + g->zf[k]) - 0.5 * (g->zf[k] + g->zf[k - 1]);
+            const double dzm = m.zf[k] - m.zf[k - 1];
+            const double dzf = 0.5 * (m.zf[k + 1] + m.zf[k]) - 0.5 * (m.zf[k] + m.zf[k - 1]);
             at(hv::VM_DZF, k) = dzf;
             at(hv::VM_RDZF, k) = 1.0 / dzf;
             at(hv::VM_A, k) = dzm / (dzm + dz);
@@ -194,65 +245,516 @@ void fill_vmet(hv_grid *g, const double *rho, const double *rt, const double *p,
     }
 }
 
-hipError_t sync(hv_grid *g) { return hipStreamSynchronize(g->stream); }
+hipError_t sync(hv_ens *e) { return hipStreamSynchronize(e->stream); }
 
-hipError_t take_event(hv_grid *g, hipEvent_t *e)
+hv::Group group_launch(const hv_ens *e, const GroupHost &g, int kind)
 {
-    if (!g->pool.empty()) {
-        *e = g->pool.back();
-        g->pool.pop_back();
+    hv::Group gr;
+    gr.mem = e->d_mem;
+    gr.ids = g.d_ids;
+    gr.nm = (int)g.ids.size();
+    if (kind < 0) {
+        gr.prefix = g.d_pprefix;
+        gr.nblocks = g.npblocks;
+        gr.ti_log2 = 4;
+    } else {
+        const int sh = g.shape[kind];
+        gr.prefix = g.d_prefix[sh];
+        gr.nblocks = g.nblocks[sh];
+        gr.ti_log2 = kShapes[sh];
+    }
+    return gr;
+}
+
+// ---- tracing ----
+hipError_t take_event(hv_ens *e, hipEvent_t *ev)
+{
+    if (!e->pool.empty()) {
+        *ev = e->pool.back();
+        e->pool.pop_back();
         return hipSuccess;
     }
-    return hipEventCreate(e);
+    return hipEventCreate(ev);
 }
 
-// Run one launch, bracketed by events when tracing is on.
 template <class F>
-hipError_t traced(hv_grid *g, int kind, F &&launch)
+hipError_t traced(hv_ens *e, hipStream_t s, int kind, F &&launch)
 {
-    if (!g->tracing) return launch();
+    if (!e->tracing) return launch();
     hipEvent_t a, b;
-    hipError_t e = take_event(g, &a);
-    if (e != hipSuccess) return e;
-    e = take_event(g, &b);
-    if (e != hipSuccess) return e;
-    e = hipEventRecord(a, g->stream);
-    if (e != hipSuccess) return e;
-    e = launch();
-    if (e != hipSuccess) return e;
-    e = hipEventRecord(b, g->stream);
-    if (e != hipSuccess) return e;
-    g->pending.push_back({kind, a, b});
+    hipError_t r = take_event(e, &a);
+    if (r != hipSuccess) return r;
+    r = take_event(e, &b);
+    if (r != hipSuccess) { e->pool.push_back(a); return r; }
+    if ((r = hipEventRecord(a, s)) != hipSuccess) return r;
+    if ((r = launch()) != hipSuccess) return r;
+    if ((r = hipEventRecord(b, s)) != hipSuccess) return r;
+    e->pending.push_back({kind, a, b});
     return hipSuccess;
 }
 
-hipError_t fold_trace(hv_grid *g)
+hipError_t fold_trace(hv_ens *e)
 {
-    hipError_t e = sync(g);
-    if (e != hipSuccess) return e;
-    for (auto &p : g->pending) {
+    hipError_t r = sync(e);
+    if (r != hipSuccess) return r;
+    for (auto &p : e->pending) {
         float ms = 0.f;
-        e = hipEventElapsedTime(&ms, p.a, p.b);
-        if (e != hipSuccess) return e;
-        g->trace_ms[p.kind] += ms;
-        g->trace_n[p.kind] += 1;
-        g->pool.push_back(p.a);
-        g->pool.push_back(p.b);
+        if ((r = hipEventElapsedTime(&ms, p.a, p.b)) != hipSuccess) return r;
+        e->trace_ms[p.kind] += ms;
+        e->trace_n[p.kind] += 1;
+        e->pool.push_back(p.a);
+        e->pool.push_back(p.b);
     }
-    g->pending.clear();
+    e->pending.clear();
     return hipSuccess;
+}
+
+// Enqueue one long step of every member on stream s.
+hipError_t enqueue_long_step(hv_ens *e, int n_short, hipStream_t s)
+{
+    hipError_t r = hipSuccess;
+    for (int st = 0; st < 3; ++st) {
+        for (auto &g : e->groups) {
+            const hv::Group gp = group_launch(e, g, KIND_PREP), gf = group_launch(e, g, KIND_FLUX);
+            r = traced(e, s, HV_K_SLOW_PREP,
+                       [&] { return hv::launch_slow_prep(e->prec, e->layout, g.L, gp, st, n_short, s); });
+            if (r != hipSuccess) return r;
+            r = traced(e, s, HV_K_SLOW_FLUX,
+                       [&] { return hv::launch_slow_flux(e->prec, e->layout, g.L, gf, st, n_short, s); });
+            if (r != hipSuccess) return r;
+        }
+        for (int q = 0; q < n_short; ++q)
+            for (auto &g : e->groups) {
+                const hv::Group gs = group_launch(e, g, KIND_SHORT);
+                r = traced(e, s, HV_K_SHORT_STEP, [&] {
+                    return hv::launch_short_step(e->prec, e->layout, g.L, gs, st, q, n_short, s);
+                });
+                if (r != hipSuccess) return r;
+            }
+    }
+    r = hv::launch_rotate(e->d_mem, e->n, n_short, s);
+    if (r != hipSuccess) return r;
+    for (auto &g : e->groups) {
+        const hv::Group gm = group_launch(e, g, -1);
+        r = traced(e, s, HV_K_MASS, [&] { return hv::launch_sums(e->prec, e->layout, g.L, gm, false, s); });
+        if (r != hipSuccess) return r;
+    }
+    return hipSuccess;
+}
+
+void mirror_rotate(hv_ens *e, int n_short)
+{
+    for (auto &m : e->m) {
+        const int cur = m.roles[1 + ((n_short - 1) & 1)];
+        const int a = m.roles[0], b = m.roles[1 + (n_short & 1)];
+        m.roles[0] = cur;
+        m.roles[1] = a;
+        m.roles[2] = b;
+    }
+}
+
+// ---- autotuner cache: one line per key, "key ti_prep ti_flux ti_short" ----
+std::string cache_path()
+{
+    if (const char *p = std::getenv("HV_TUNE_CACHE")) return p;
+    if (const char *h = std::getenv("HOME")) return std::string(h) + "/.cache/hevi/tune.txt";
+    return "";
+}
+
+std::string tune_key(const hv_ens *e, const GroupHost &g)
+{
+    size_t cols = 0;
+    for (int q : g.ids) cols += (size_t)e->m[q].nx * e->m[q].ny;
+    // bucket the group size by powers of two
+    int b = 0;
+    while ((size_t(1) << (b + 1)) <= cols) ++b;
+    std::ostringstream k;
+    k << "gfx950:p" << e->prec << ":l" << e->layout << ":L" << g.L << ":c2^" << b << ":m" << g.ids.size();
+    return k.str();
+}
+
+bool cache_lookup(const std::string &key, int shape[NKIND])
+{
+    const std::string path = cache_path();
+    if (path.empty()) return false;
+    std::ifstream f(path);
+    std::string k;
+    int a, b, c;
+    bool found = false;
+    while (f >> k >> a >> b >> c)
+        if (k == key && a >= 0 && a < 3 && b >= 0 && b < 3 && c >= 0 && c < 3) {
+            shape[0] = a; shape[1] = b; shape[2] = c;
+            found = true;
+        }
+    return found;
+}
+
+void cache_store(const std::string &key, const int shape[NKIND])
+{
+    const std::string path = cache_path();
+    if (path.empty()) return;
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos) {
+        const std::string dir = path.substr(0, slash);
+        std::string cmd = "mkdir -p '" + dir + "' 2>/dev/null";
+        if (dir.find('\'') == std::string::npos) (void)std::system(cmd.c_str());
+    }
+    std::ofstream f(path, std::ios::app);
+    if (f) f << key << ' ' << shape[0] << ' ' << shape[1] << ' ' << shape[2] << '\n';
+}
+
+// ---- creation ----
+int ens_create(hv_ens *e, int n, const hv_grid_desc *descs, void *ws, size_t bytes, void *stream)
+{
+    if (n < 1) return fail(nullptr, HV_ERR_ARG, "member count must be >= 1");
+    if (!descs) return fail(nullptr, HV_ERR_ARG, "descs is NULL");
+    for (int q = 0; q < n; ++q) {
+        std::string why = check_desc(&descs[q]);
+        if (!why.empty()) return fail(nullptr, HV_ERR_ARG, (n > 1 ? "member " + std::to_string(q) + ": " : "") + why);
+        if (descs[q].precision != descs[0].precision || descs[q].layout != descs[0].layout)
+            return fail(nullptr, HV_ERR_ARG, "all members must share precision and layout");
+        if (unsupported(&descs[q], &why)) return fail(nullptr, HV_ERR_UNSUPPORTED, why);
+    }
+    const Plan p = make_plan(n, descs);
+    if (!ws) return fail(nullptr, HV_ERR_ARG, "workspace is NULL");
+    if (((uintptr_t)ws) % kAlign) return fail(nullptr, HV_ERR_ARG, "workspace not 256-byte aligned");
+    if (bytes < p.total) {
+        char b[160];
+        std::snprintf(b, sizeof b, "workspace too small: %zu bytes given, %zu needed", bytes, p.total);
+        return fail(nullptr, HV_ERR_ARG, b);
+    }
+    char *base = (char *)ws;
+    e->n = n;
+    e->prec = descs[0].precision;
+    e->layout = descs[0].layout;
+    e->esize = elem_size(e->prec);
+    e->stream = (hipStream_t)stream;
+    e->d_mem = (hv::MemberDev *)(base + p.table);
+    e->m.resize(n);
+    for (int q = 0; q < n; ++q) {
+        MemberHost &m = e->m[q];
+        const hv_grid_desc &d = descs[q];
+        m.nx = d.nx; m.ny = d.ny; m.nz = d.nz; m.L = d.nz / hv::kSeg;
+        m.dx = d.dx; m.dy = d.dy; m.beta = d.beta;
+        m.zf.assign(d.zeta_faces, d.zeta_faces + d.nz + 1);
+        m.ncell = (size_t)d.nx * d.ny * d.nz;
+        Carve c;
+        c.off = p.member_off[q];
+        hv::MemberDev &v = m.dev;
+        v.nx = m.nx; v.ny = m.ny; v.nz = m.nz;
+        v.npart = hv::partials_of(m.nx, m.ny);
+        v.roles[0] = 0; v.roles[1] = 1; v.roles[2] = 2; v.roles[3] = 0;
+        v.rdx = 1.0 / m.dx; v.rdy = 1.0 / m.dy; v.beta = m.beta; v.dt = 0.0;
+        for (int b = 0; b < 3; ++b)
+            for (int f = 0; f < 5; ++f) v.st[b][f] = base + c.take(m.ncell * e->esize);
+        for (int f = 0; f < 7; ++f) v.slow[f] = base + c.take(m.ncell * e->esize);
+        for (int f = 0; f < 3; ++f) v.spec[f] = base + c.take(m.ncell * e->esize);
+        v.vm = (const double *)(base + c.take(sizeof(double) * hv::VM_NFIELDS * m.nz));
+        v.partials = (double *)(base + c.take(sizeof(double) * (size_t)v.npart));
+        v.sums = (double *)(base + c.take(sizeof(double) * 4));
+    }
+    auto gm = group_members(n, descs);
+    e->groups.resize(gm.size());
+    for (size_t gi = 0; gi < gm.size(); ++gi) {
+        GroupHost &g = e->groups[gi];
+        g.ids = gm[gi];
+        g.L = descs[g.ids[0]].nz / hv::kSeg;
+        const int nm = (int)g.ids.size();
+        int *dst = (int *)(base + p.group_off[gi]);
+        g.d_ids = dst;
+        for (int s = 0; s < 3; ++s) g.d_prefix[s] = dst + nm + s * (nm + 1);
+        g.d_pprefix = dst + nm + 3 * (nm + 1);
+        std::vector<int> h(nm + 4 * (nm + 1), 0);
+        for (int a = 0; a < nm; ++a) h[a] = g.ids[a];
+        for (int s = 0; s < 3; ++s) {
+            int acc = 0;
+            for (int a = 0; a < nm; ++a) {
+                h[nm + s * (nm + 1) + a] = acc;
+                acc += hv::tiles_of(e->m[g.ids[a]].nx, e->m[g.ids[a]].ny, kShapes[s]);
+            }
+            h[nm + s * (nm + 1) + nm] = acc;
+            g.nblocks[s] = acc;
+        }
+        int acc = 0;
+        for (int a = 0; a < nm; ++a) {
+            h[nm + 3 * (nm + 1) + a] = acc;
+            acc += e->m[g.ids[a]].dev.npart;
+        }
+        h[nm + 3 * (nm + 1) + nm] = acc;
+        g.npblocks = acc;
+        hipError_t r = hipMemcpyAsync(dst, h.data(), h.size() * sizeof(int), hipMemcpyHostToDevice, e->stream);
+        if (r == hipSuccess) r = sync(e);
+        if (r != hipSuccess) return hip_fail(nullptr, r, "upload group tables");
+        int shape[NKIND];
+        if (cache_lookup(tune_key(e, g), shape)) std::copy(shape, shape + NKIND, g.shape);
+    }
+    std::vector<hv::MemberDev> table(n);
+    for (int q = 0; q < n; ++q) table[q] = e->m[q].dev;
+    hipError_t r = hipMemcpyAsync(e->d_mem, table.data(), sizeof(hv::MemberDev) * n,
+                                  hipMemcpyHostToDevice, e->stream);
+    if (r == hipSuccess) r = sync(e);
+    if (r != hipSuccess) return hip_fail(nullptr, r, "upload member table");
+    if ((r = hipStreamCreateWithFlags(&e->own, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(nullptr, r, "hipStreamCreateWithFlags");
+    if ((r = hipEventCreateWithFlags(&e->fork, hipEventDisableTiming)) != hipSuccess ||
+        (r = hipEventCreateWithFlags(&e->join, hipEventDisableTiming)) != hipSuccess)
+        return hip_fail(nullptr, r, "hipEventCreate");
+    return HV_OK;
+}
+
+int member_init(hv_ens *e, int q, const double *const fields[5], const double *rho_ref,
+                const double *rhotheta_ref, const double *p_ref)
+{
+    if (q < 0 || q >= e->n) return fail(e, HV_ERR_ARG, "member index out of range");
+    if (!fields || !rho_ref || !rhotheta_ref || !p_ref) return fail(e, HV_ERR_ARG, "NULL input array");
+    for (int f = 0; f < 5; ++f)
+        if (!fields[f]) return fail(e, HV_ERR_ARG, "NULL field pointer");
+    MemberHost &m = e->m[q];
+    const size_t nxy = (size_t)m.nx * m.ny;
+    for (int k = 0; k < m.nz; ++k)
+        if (!std::isfinite(rho_ref[k]) || !(rho_ref[k] > 0) || !std::isfinite(p_ref[k]) ||
+            !(p_ref[k] > 0) || !std::isfinite(rhotheta_ref[k]) || !(rhotheta_ref[k] > 0))
+            return fail(e, HV_ERR_ARG, "reference columns must be finite and positive");
+    for (int f = 0; f < 5; ++f) {
+        const size_t cnt = (f == HV_RHOW ? nxy * (m.nz + 1) : nxy * m.nz);
+        for (size_t c = 0; c < cnt; ++c)
+            if (!std::isfinite(fields[f][c])) return fail(e, HV_ERR_ARG, "non-finite value in a field");
+    }
+    for (size_t c = 0; c < nxy; ++c)
+        if (fields[HV_RHOW][c] != 0.0 || fields[HV_RHOW][nxy * m.nz + c] != 0.0)
+            return fail(e, HV_ERR_ARG, "rho*w must be 0 on both lids");
+    hipError_t r = sync(e);   // no step of this ensemble may still read the buffers
+    if (r != hipSuccess) return hip_fail(e, r, "stream synchronize");
+    std::vector<double> vm;
+    fill_vmet(m, rho_ref, rhotheta_ref, p_ref, vm);
+    r = hipMemcpy((void *)m.dev.vm, vm.data(), vm.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (r != hipSuccess) return hip_fail(e, r, "hipMemcpy(vmet)");
+    std::vector<double> bd;
+    std::vector<float> bf;
+    if (e->prec == HV_FP64) bd.resize(m.ncell);
+    else bf.resize(m.ncell);
+    const int P = m.roles[0];
+    for (int f = 0; f < 5; ++f) {
+        const void *src;
+        if (e->prec == HV_FP64) { to_device_order(e->layout, m, fields[f], bd.data()); src = bd.data(); }
+        else { to_device_order(e->layout, m, fields[f], bf.data()); src = bf.data(); }
+        r = hipMemcpy(m.dev.st[P][f], src, m.ncell * e->esize, hipMemcpyHostToDevice);
+        if (r != hipSuccess) return hip_fail(e, r, "hipMemcpy(state)");
+    }
+    double s = 0.0, c = 0.0;
+    for (int k = 0; k < m.nz; ++k) {
+        const double x = rho_ref[k] * (m.dx * m.dy * (m.zf[k + 1] - m.zf[k])) * (double)nxy;
+        const double t = s + x;
+        c += (std::fabs(s) >= std::fabs(x)) ? ((s - t) + x) : ((x - t) + s);
+        s = t;
+    }
+    m.mass_ref = s + c;
+    m.have_state = true;
+    for (auto &g : e->groups) {
+        const hv::Group gm = group_launch(e, g, -1);
+        r = hv::launch_sums(e->prec, e->layout, g.L, gm, false, e->stream);
+        if (r != hipSuccess) return hip_fail(e, r, "mass after state_init");
+    }
+    if ((r = sync(e)) != hipSuccess) return hip_fail(e, r, "mass after state_init");
+    return HV_OK;
+}
+
+int ens_step(hv_ens *e, const double *dts, int n_long, int n_short)
+{
+    for (int q = 0; q < e->n; ++q) {
+        if (!e->m[q].have_state) return fail(e, HV_ERR_STATE, "step before every member's state_init");
+        if (!(dts[q] > 0.0) || !std::isfinite(dts[q])) return fail(e, HV_ERR_ARG, "dt must be positive");
+    }
+    if (n_long < 0) return fail(e, HV_ERR_ARG, "n_long must be >= 0");
+    if (n_short < 1) return fail(e, HV_ERR_ARG, "n_short must be >= 1");
+    hipError_t r;
+    for (int q = 0; q < e->n; ++q) {
+        MemberHost &m = e->m[q];
+        if (m.dt != dts[q]) {
+            m.dt = dts[q];
+            m.dev.dt = m.dt;
+            // a kernel argument is captured at launch, so no host buffer must outlive the call
+            r = hv::launch_set_dt(e->d_mem, q, m.dt, e->stream);
+            if (r != hipSuccess) return hip_fail(e, r, "set dt");
+        }
+    }
+    if (n_long == 0) return HV_OK;
+    if (e->tracing) {
+        for (int s = 0; s < n_long; ++s) {
+            if ((r = enqueue_long_step(e, n_short, e->stream)) != hipSuccess) return hip_fail(e, r, "long step");
+            mirror_rotate(e, n_short);
+        }
+        return HV_OK;
+    }
+    if (!e->exec || e->graph_nshort != n_short) {
+        if (e->exec) {
+            (void)hipGraphExecDestroy(e->exec);
+            e->exec = nullptr;
+        }
+        hipGraph_t graph = nullptr;
+        if ((r = hipStreamBeginCapture(e->own, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return hip_fail(e, r, "hipStreamBeginCapture");
+        hipError_t rl = enqueue_long_step(e, n_short, e->own);
+        r = hipStreamEndCapture(e->own, &graph);
+        if (rl != hipSuccess) { if (graph) (void)hipGraphDestroy(graph); return hip_fail(e, rl, "capture long step"); }
+        if (r != hipSuccess) return hip_fail(e, r, "hipStreamEndCapture");
+        r = hipGraphInstantiate(&e->exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (r != hipSuccess) { e->exec = nullptr; return hip_fail(e, r, "hipGraphInstantiate"); }
+        e->graph_nshort = n_short;
+    }
+    // order the private stream after the caller's work, replay, then back
+    if ((r = hipEventRecord(e->fork, e->stream)) != hipSuccess) return hip_fail(e, r, "hipEventRecord");
+    if ((r = hipStreamWaitEvent(e->own, e->fork, 0)) != hipSuccess) return hip_fail(e, r, "hipStreamWaitEvent");
+    for (int s = 0; s < n_long; ++s) {
+        if ((r = hipGraphLaunch(e->exec, e->own)) != hipSuccess) return hip_fail(e, r, "hipGraphLaunch");
+        mirror_rotate(e, n_short);
+    }
+    if ((r = hipEventRecord(e->join, e->own)) != hipSuccess) return hip_fail(e, r, "hipEventRecord");
+    if ((r = hipStreamWaitEvent(e->stream, e->join, 0)) != hipSuccess) return hip_fail(e, r, "hipStreamWaitEvent");
+    return HV_OK;
+}
+
+int member_read(hv_ens *e, int q, int field, double *out)
+{
+    if (q < 0 || q >= e->n) return fail(e, HV_ERR_ARG, "member index out of range");
+    if (!out) return fail(e, HV_ERR_ARG, "host_out is NULL");
+    if (field < HV_RHO_PTB || field > HV_RHOTHETA_PTB) return fail(e, HV_ERR_ARG, "unknown field id");
+    MemberHost &m = e->m[q];
+    if (!m.have_state) return fail(e, HV_ERR_STATE, "read before state_init");
+    hipError_t r = sync(e);
+    if (r != hipSuccess) return hip_fail(e, r, "stream synchronize");
+    const void *src = m.dev.st[m.roles[0]][field];
+    if (e->prec == HV_FP64) {
+        std::vector<double> b(m.ncell);
+        if ((r = hipMemcpy(b.data(), src, m.ncell * 8, hipMemcpyDeviceToHost)) != hipSuccess)
+            return hip_fail(e, r, "hipMemcpy(read)");
+        from_device_order(e->layout, m, b.data(), out);
+    } else {
+        std::vector<float> b(m.ncell);
+        if ((r = hipMemcpy(b.data(), src, m.ncell * 4, hipMemcpyDeviceToHost)) != hipSuccess)
+            return hip_fail(e, r, "hipMemcpy(read)");
+        from_device_order(e->layout, m, b.data(), out);
+    }
+    if (field == HV_RHOW) {
+        const size_t nxy = (size_t)m.nx * m.ny;
+        for (size_t c = 0; c < nxy; ++c) out[nxy * m.nz + c] = 0.0;
+    }
+    return HV_OK;
+}
+
+int member_mass(hv_ens *e, int q, double *mass, double *energy)
+{
+    if (q < 0 || q >= e->n) return fail(e, HV_ERR_ARG, "member index out of range");
+    MemberHost &m = e->m[q];
+    if (!m.have_state) return fail(e, HV_ERR_STATE, "mass before state_init");
+    hipError_t r;
+    if (energy)
+        for (auto &g : e->groups) {
+            const hv::Group gm = group_launch(e, g, -1);
+            if ((r = hv::launch_sums(e->prec, e->layout, g.L, gm, true, e->stream)) != hipSuccess)
+                return hip_fail(e, r, "energy sum");
+        }
+    double h[2] = {0.0, 0.0};
+    r = hipMemcpyAsync(h, m.dev.sums, 2 * sizeof(double), hipMemcpyDeviceToHost, e->stream);
+    if (r == hipSuccess) r = sync(e);
+    if (r != hipSuccess) return hip_fail(e, r, "read sums");
+    const double ms = m.mass_ref + h[0];
+    if (mass) *mass = ms;
+    if (energy) *energy = h[1];
+    if (!std::isfinite(ms)) return fail(e, HV_ERR_NONFINITE, "mass sum is not finite");
+    return HV_OK;
+}
+
+// Time one kernel kind of one group for every tile shape; keep the fastest.
+int tune(hv_ens *e, int32_t *out, int32_t *ngroups)
+{
+    for (int q = 0; q < e->n; ++q)
+        if (!e->m[q].have_state) return fail(e, HV_ERR_STATE, "tune before every member's state_init");
+    hipError_t r = sync(e);
+    if (r != hipSuccess) return hip_fail(e, r, "stream synchronize");
+    const bool was_tracing = e->tracing;
+    e->tracing = false;
+    hipEvent_t a, b;
+    if ((r = hipEventCreate(&a)) != hipSuccess) return hip_fail(e, r, "hipEventCreate");
+    if ((r = hipEventCreate(&b)) != hipSuccess) { (void)hipEventDestroy(a); return hip_fail(e, r, "hipEventCreate"); }
+    const int n_short = 6;
+    auto launch = [&](const GroupHost &g, int kind, hipStream_t s) -> hipError_t {
+        const hv::Group gr = group_launch(e, g, kind);
+        if (kind == KIND_PREP) return hv::launch_slow_prep(e->prec, e->layout, g.L, gr, 0, n_short, s);
+        if (kind == KIND_FLUX) return hv::launch_slow_flux(e->prec, e->layout, g.L, gr, 0, n_short, s);
+        return hv::launch_short_step(e->prec, e->layout, g.L, gr, 0, 0, n_short, s);
+    };
+    int rc = HV_OK;
+    for (auto &g : e->groups) {
+        for (int kind = 0; kind < NKIND && rc == HV_OK; ++kind) {
+            float best = 1e30f;
+            int best_s = g.shape[kind];
+            for (int s = 0; s < 3 && rc == HV_OK; ++s) {
+                g.shape[kind] = s;
+                // the slow arrays the flux and short step read must hold this stage's values
+                if ((r = launch(g, KIND_PREP, e->stream)) != hipSuccess ||
+                    (kind == KIND_SHORT && (r = launch(g, KIND_FLUX, e->stream)) != hipSuccess) ||
+                    (r = launch(g, kind, e->stream)) != hipSuccess ||
+                    (r = hipEventRecord(a, e->stream)) != hipSuccess) { rc = hip_fail(e, r, "tune"); break; }
+                for (int rep = 0; rep < 3; ++rep)
+                    if ((r = launch(g, kind, e->stream)) != hipSuccess) break;
+                if (r == hipSuccess) r = hipEventRecord(b, e->stream);
+                if (r == hipSuccess) r = hipEventSynchronize(b);
+                float ms = 0.f;
+                if (r == hipSuccess) r = hipEventElapsedTime(&ms, a, b);
+                if (r != hipSuccess) { rc = hip_fail(e, r, "tune"); break; }
+                if (ms < best) { best = ms; best_s = s; }
+            }
+            g.shape[kind] = best_s;
+        }
+        if (rc != HV_OK) break;
+        cache_store(tune_key(e, g), g.shape);
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    e->tracing = was_tracing;
+    if (rc != HV_OK) return rc;
+    if (e->exec) {
+        (void)hipGraphExecDestroy(e->exec);
+        e->exec = nullptr;
+    }
+    if (ngroups) *ngroups = (int32_t)e->groups.size();
+    if (out)
+        for (size_t gi = 0; gi < e->groups.size(); ++gi)
+            for (int k = 0; k < NKIND; ++k) out[gi * NKIND + k] = 1 << kShapes[e->groups[gi].shape[k]];
+    return HV_OK;
+}
+
+int trace_on(hv_ens *e, int32_t on)
+{
+    if (on) {
+        hipError_t r = fold_trace(e);
+        if (r != hipSuccess) return hip_fail(e, r, "trace");
+        for (int k = 0; k < HV_K_COUNT; ++k) { e->trace_ms[k] = 0.0; e->trace_n[k] = 0; }
+    }
+    e->tracing = on != 0;
+    return HV_OK;
+}
+
+int trace_read(hv_ens *e, int32_t kind, double *ms, int64_t *n)
+{
+    if (kind < 0 || kind >= HV_K_COUNT) return fail(e, HV_ERR_ARG, "unknown kernel kind");
+    hipError_t r = fold_trace(e);
+    if (r != hipSuccess) return hip_fail(e, r, "trace read");
+    if (ms) *ms = e->trace_ms[kind];
+    if (n) *n = e->trace_n[kind];
+    return HV_OK;
 }
 
 }  // namespace
 
 extern "C" {
 
+// ---------------------------------------------------------------- grid ---
 size_t hv_workspace_bytes(const hv_grid_desc *desc)
 {
-    std::string why = check_desc(desc);
-    if (!why.empty()) { g_global_error = why; return 0; }
-    size_t offs[kNOffs];
-    return plan(desc, offs);
+    return hv_ens_workspace_bytes(1, desc);
 }
 
 int hv_grid_create(const hv_grid_desc *desc, void *dev_workspace, size_t bytes, void *hip_stream,
@@ -260,37 +762,10 @@ int hv_grid_create(const hv_grid_desc *desc, void *dev_workspace, size_t bytes, 
 {
     if (!out) return fail(nullptr, HV_ERR_ARG, "out is NULL");
     *out = nullptr;
-    std::string why = check_desc(desc);
-    if (!why.empty()) return fail(nullptr, HV_ERR_ARG, why);
-    if (unsupported(desc, &why)) return fail(nullptr, HV_ERR_UNSUPPORTED, why);
-    size_t offs[kNOffs];
-    const size_t need = plan(desc, offs);
-    if (!dev_workspace) return fail(nullptr, HV_ERR_ARG, "workspace is NULL");
-    if (((uintptr_t)dev_workspace) % kAlign) return fail(nullptr, HV_ERR_ARG, "workspace not 256-byte aligned");
-    if (bytes < need) {
-        char b[160];
-        std::snprintf(b, sizeof b, "workspace too small: %zu bytes given, %zu needed", bytes, need);
-        return fail(nullptr, HV_ERR_ARG, b);
-    }
     hv_grid *g = new (std::nothrow) hv_grid();
     if (!g) return fail(nullptr, HV_ERR_ARG, "out of host memory");
-    g->nx = desc->nx; g->ny = desc->ny; g->nz = desc->nz;
-    g->dx = desc->dx; g->dy = desc->dy; g->beta = desc->beta;
-    g->prec = desc->precision; g->layout = desc->layout;
-    g->esize = elem_size(g->prec);
-    g->ncell = (size_t)g->nx * g->ny * g->nz;
-    g->stream = (hipStream_t)hip_stream;
-    g->zf.assign(desc->zeta_faces, desc->zeta_faces + desc->nz + 1);
-    g->geom = hv::Geom{g->nx, g->ny, g->nz, 1.0 / g->dx, 1.0 / g->dy, g->beta};
-    char *ws = (char *)dev_workspace;
-    int q = 0;
-    for (int b = 0; b < 3; ++b)
-        for (int f = 0; f < 5; ++f) g->state[b][f] = ws + offs[q++];
-    for (int f = 0; f < 7; ++f) g->slow[f] = ws + offs[q++];
-    for (int f = 0; f < 3; ++f) g->spec[f] = ws + offs[q++];
-    g->vm = (double *)(ws + offs[q++]);
-    g->partials = (double *)(ws + offs[q++]);
-    g->sums = (double *)(ws + offs[q++]);
+    const int rc = ens_create(g, 1, desc, dev_workspace, bytes, hip_stream);
+    if (rc != HV_OK) { delete g; return rc; }
     *out = g;
     return HV_OK;
 }
@@ -299,199 +774,124 @@ int hv_state_init(hv_grid_t g, const double *const fields[5], const double *rho_
                   const double *rhotheta_ref, const double *p_ref)
 {
     if (!g) return fail(nullptr, HV_ERR_ARG, "handle is NULL");
-    if (!fields || !rho_ref || !rhotheta_ref || !p_ref) return fail(g, HV_ERR_ARG, "NULL input array");
-    for (int f = 0; f < 5; ++f)
-        if (!fields[f]) return fail(g, HV_ERR_ARG, "NULL field pointer");
-    const int nx = g->nx, ny = g->ny, nz = g->nz;
-    const size_t nxy = (size_t)nx * ny;
-    for (int k = 0; k < nz; ++k)
-        if (!std::isfinite(rho_ref[k]) || !(rho_ref[k] > 0) || !std::isfinite(p_ref[k]) ||
-            !(p_ref[k] > 0) || !std::isfinite(rhotheta_ref[k]) || !(rhotheta_ref[k] > 0))
-            return fail(g, HV_ERR_ARG, "reference columns must be finite and positive");
-    for (int f = 0; f < 5; ++f) {
-        const size_t n = (f == HV_RHOW ? nxy * (nz + 1) : nxy * nz);
-        for (size_t q = 0; q < n; ++q)
-            if (!std::isfinite(fields[f][q])) return fail(g, HV_ERR_ARG, "non-finite value in a field");
-    }
-    for (size_t q = 0; q < nxy; ++q)
-        if (fields[HV_RHOW][q] != 0.0 || fields[HV_RHOW][nxy * nz + q] != 0.0)
-            return fail(g, HV_ERR_ARG, "rho*w must be 0 on both lids");
-
-    std::vector<double> vm;
-    fill_vmet(g, rho_ref, rhotheta_ref, p_ref, vm);
-    hipError_t e = hipMemcpyAsync(g->vm, vm.data(), vm.size() * sizeof(double), hipMemcpyHostToDevice,
-                                  g->stream);
-    if (e != hipSuccess) return hip_fail(g, e, "hipMemcpyAsync(vmet)");
-
-    // convert each field to the device layout and precision, then copy in
-    std::vector<double> bd;
-    std::vector<float> bf;
-    if (g->prec == HV_FP64) bd.resize(g->ncell);
-    else bf.resize(g->ncell);
-    g->cur = 0;
-    for (int f = 0; f < 5; ++f) {
-        const void *src;
-        if (g->prec == HV_FP64) { to_device_order(g, fields[f], bd.data()); src = bd.data(); }
-        else { to_device_order(g, fields[f], bf.data()); src = bf.data(); }
-        e = hipMemcpyAsync(g->state[0][f], src, g->ncell * g->esize, hipMemcpyHostToDevice, g->stream);
-        if (e == hipSuccess) e = sync(g);   // staging buffer is reused by the next field
-        if (e != hipSuccess) return hip_fail(g, e, "hipMemcpyAsync(state)");
-    }
-    // constant part of the mass, summed on the host with compensation
-    double s = 0.0, c = 0.0;
-    for (int k = 0; k < nz; ++k) {
-        const double x = rho_ref[k] * (g->dx * g->dy * (g->zf[k + 1] - g->zf[k])) * (double)nxy;
-        const double t = s + x;
-        c += (std::fabs(s) >= std::fabs(x)) ? ((s - t) + x) : ((x - t) + s);
-        s = t;
-    }
-    g->mass_ref = s + c;
-    e = hv::launch_mass(g->prec, g->layout, g->geom, g->vm, g->state[0][HV_RHO_PTB], g->partials,
-                        g->sums, g->stream);
-    if (e == hipSuccess) e = sync(g);
-    if (e != hipSuccess) return hip_fail(g, e, "mass after state_init");
-    g->have_state = true;
-    g->any_nonfinite = false;
-    return HV_OK;
+    return member_init(g, 0, fields, rho_ref, rhotheta_ref, p_ref);
 }
 
 int hv_step(hv_grid_t g, double dt, int32_t n_long, int32_t n_short)
 {
     if (!g) return fail(nullptr, HV_ERR_ARG, "handle is NULL");
-    if (!g->have_state) return fail(g, HV_ERR_STATE, "hv_step before hv_state_init");
-    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(g, HV_ERR_ARG, "dt must be positive");
-    if (n_long < 0) return fail(g, HV_ERR_ARG, "n_long must be >= 0");
-    if (n_short < 1) return fail(g, HV_ERR_ARG, "n_short must be >= 1");
-    const double frac[3] = {1.0 / 3.0, 0.5, 1.0};
-    for (int step = 0; step < n_long; ++step) {
-        const int P = g->cur;                         // start state
-        const int R0 = (P + 1) % 3, R1 = (P + 2) % 3; // running buffers
-        int stage_in = P;
-        for (int s = 0; s < 3; ++s) {
-            void *const *in = g->state[stage_in];
-            const void *st[5] = {in[0], in[1], in[2], in[3], in[4]};
-            void *prep[6] = {g->spec[0], g->spec[1], g->spec[2], g->slow[4], g->slow[5], g->slow[6]};
-            hipError_t e = traced(g, HV_K_SLOW_PREP, [&] {
-                return hv::launch_slow_prep(g->prec, g->layout, g->geom, g->vm, st, prep, g->stream);
-            });
-            if (e != hipSuccess) return hip_fail(g, e, "slow sweep (prep)");
-            const void *uvw[3] = {in[1], in[2], in[3]};
-            const void *spec[4] = {g->spec[0], g->spec[1], g->spec[2], g->slow[4]};
-            void *fl[4] = {g->slow[0], g->slow[1], g->slow[2], g->slow[3]};
-            e = traced(g, HV_K_SLOW_FLUX, [&] {
-                return hv::launch_slow_flux(g->prec, g->layout, g->geom, g->vm, uvw, spec, fl, g->stream);
-            });
-            if (e != hipSuccess) return hip_fail(g, e, "slow sweep (flux)");
-            const double dtau = dt * frac[s] / n_short;
-            int src = P;
-            for (int q = 0; q < n_short; ++q) {
-                const int dst = (q & 1) ? R1 : R0;
-                const void *sin[5], *sl[7];
-                for (int f = 0; f < 5; ++f) sin[f] = g->state[src][f];
-                for (int f = 0; f < 7; ++f) sl[f] = g->slow[f];
-                e = traced(g, HV_K_SHORT_STEP, [&] {
-                    return hv::launch_short_step(g->prec, g->layout, g->geom, g->vm, sin, g->state[dst],
-                                                 sl, dtau, g->stream);
-                });
-                if (e != hipSuccess) return hip_fail(g, e, "short step");
-                src = dst;
-            }
-            stage_in = src;
-        }
-        g->cur = stage_in;
-        hipError_t e = traced(g, HV_K_MASS, [&] {
-            return hv::launch_mass(g->prec, g->layout, g->geom, g->vm, g->state[g->cur][HV_RHO_PTB],
-                                   g->partials, g->sums, g->stream);
-        });
-        if (e != hipSuccess) return hip_fail(g, e, "mass sum");
-    }
-    return HV_OK;
+    if (!g->m[0].have_state) return fail(g, HV_ERR_STATE, "hv_step before hv_state_init");
+    return ens_step(g, &dt, n_long, n_short);
 }
 
 int hv_state_read(hv_grid_t g, int32_t field, double *host_out)
 {
     if (!g) return fail(nullptr, HV_ERR_ARG, "handle is NULL");
-    if (!host_out) return fail(g, HV_ERR_ARG, "host_out is NULL");
-    if (field < HV_RHO_PTB || field > HV_RHOTHETA_PTB) return fail(g, HV_ERR_ARG, "unknown field id");
-    if (!g->have_state) return fail(g, HV_ERR_STATE, "hv_state_read before hv_state_init");
-    hipError_t e = sync(g);
-    if (e != hipSuccess) return hip_fail(g, e, "stream synchronize");
-    const size_t nxy = (size_t)g->nx * g->ny;
-    double *dst = host_out;
-    std::vector<double> bd;
-    std::vector<float> bf;
-    const void *src = g->state[g->cur][field];
-    if (g->prec == HV_FP64) {
-        bd.resize(g->ncell);
-        e = hipMemcpy(bd.data(), src, g->ncell * 8, hipMemcpyDeviceToHost);
-        if (e != hipSuccess) return hip_fail(g, e, "hipMemcpy(read)");
-        from_device_order(g, bd.data(), dst);
-    } else {
-        bf.resize(g->ncell);
-        e = hipMemcpy(bf.data(), src, g->ncell * 4, hipMemcpyDeviceToHost);
-        if (e != hipSuccess) return hip_fail(g, e, "hipMemcpy(read)");
-        from_device_order(g, bf.data(), dst);
-    }
-    if (field == HV_RHOW)
-        for (size_t q = 0; q < nxy; ++q) dst[nxy * g->nz + q] = 0.0;   // upper lid
-    return HV_OK;
+    return member_read(g, 0, field, host_out);
 }
 
 int hv_mass(hv_grid_t g, double *mass_out, double *energy_out)
 {
     if (!g) return fail(nullptr, HV_ERR_ARG, "handle is NULL");
-    if (!g->have_state) return fail(g, HV_ERR_STATE, "hv_mass before hv_state_init");
-    hipError_t e = hipSuccess;
-    if (energy_out) {
-        void *const *st = g->state[g->cur];
-        const void *cst[5] = {st[0], st[1], st[2], st[3], st[4]};
-        e = hv::launch_energy(g->prec, g->layout, g->geom, g->vm, cst, g->partials, g->sums + 1,
-                              g->stream);
-        if (e != hipSuccess) return hip_fail(g, e, "energy sum");
-    }
-    double h[2] = {0.0, 0.0};
-    e = hipMemcpyAsync(h, g->sums, 2 * sizeof(double), hipMemcpyDeviceToHost, g->stream);
-    if (e == hipSuccess) e = sync(g);
-    if (e != hipSuccess) return hip_fail(g, e, "read sums");
-    const double m = g->mass_ref + h[0];
-    if (mass_out) *mass_out = m;
-    if (energy_out) *energy_out = h[1];
-    if (!std::isfinite(m)) {
-        g->any_nonfinite = true;
-    }
-    if (g->any_nonfinite) return fail(g, HV_ERR_NONFINITE, "mass sum is not finite");
-    return HV_OK;
+    return member_mass(g, 0, mass_out, energy_out);
+}
+
+int hv_tune(hv_grid_t g, int32_t *tile_x_out)
+{
+    if (!g) return fail(nullptr, HV_ERR_ARG, "handle is NULL");
+    return tune(g, tile_x_out, nullptr);
 }
 
 int hv_trace(hv_grid_t g, int32_t on)
 {
     if (!g) return fail(nullptr, HV_ERR_ARG, "handle is NULL");
-    if (on) {
-        hipError_t e = fold_trace(g);
-        if (e != hipSuccess) return hip_fail(g, e, "hv_trace");
-        for (int k = 0; k < HV_K_COUNT; ++k) { g->trace_ms[k] = 0.0; g->trace_n[k] = 0; }
-    }
-    g->tracing = on != 0;
-    return HV_OK;
+    return trace_on(g, on);
 }
 
 int hv_trace_read(hv_grid_t g, int32_t kind, double *ms_total, int64_t *launches)
 {
     if (!g) return fail(nullptr, HV_ERR_ARG, "handle is NULL");
-    if (kind < 0 || kind >= HV_K_COUNT) return fail(g, HV_ERR_ARG, "unknown kernel kind");
-    hipError_t e = fold_trace(g);
-    if (e != hipSuccess) return hip_fail(g, e, "hv_trace_read");
-    if (ms_total) *ms_total = g->trace_ms[kind];
-    if (launches) *launches = g->trace_n[kind];
-    return HV_OK;
+    return trace_read(g, kind, ms_total, launches);
 }
 
 void hv_grid_destroy(hv_grid_t g) { delete g; }
 
-const char *hv_last_error(hv_grid_t g)
+const char *hv_last_error(hv_grid_t g) { return g ? g->err.c_str() : g_global_error.c_str(); }
+
+// ------------------------------------------------------------ ensemble ---
+size_t hv_ens_workspace_bytes(int32_t n, const hv_grid_desc *descs)
 {
-    if (!g) return g_global_error.c_str();
-    return g->err.c_str();
+    if (n < 1 || !descs) { g_global_error = "need n >= 1 member descriptions"; return 0; }
+    for (int q = 0; q < n; ++q) {
+        std::string why = check_desc(&descs[q]);
+        if (!why.empty()) { g_global_error = (n > 1 ? "member " + std::to_string(q) + ": " : "") + why; return 0; }
+        if (descs[q].precision != descs[0].precision || descs[q].layout != descs[0].layout) {
+            g_global_error = "all members must share precision and layout";
+            return 0;
+        }
+    }
+    return make_plan(n, descs).total;
 }
+
+int hv_ens_create(int32_t n, const hv_grid_desc *descs, void *ws, size_t bytes, void *stream,
+                  hv_ens_t *out)
+{
+    if (!out) return fail(nullptr, HV_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    hv_ens *e = new (std::nothrow) hv_ens();
+    if (!e) return fail(nullptr, HV_ERR_ARG, "out of host memory");
+    const int rc = ens_create(e, n, descs, ws, bytes, stream);
+    if (rc != HV_OK) { delete e; return rc; }
+    *out = e;
+    return HV_OK;
+}
+
+int hv_ens_state_init(hv_ens_t e, int32_t member, const double *const fields[5],
+                      const double *rho_ref, const double *rhotheta_ref, const double *p_ref)
+{
+    if (!e) return fail(nullptr, HV_ERR_ARG, "handle is NULL");
+    return member_init(e, member, fields, rho_ref, rhotheta_ref, p_ref);
+}
+
+int hv_ens_step(hv_ens_t e, const double *dt_per_member, int32_t n_long, int32_t n_short)
+{
+    if (!e) return fail(nullptr, HV_ERR_ARG, "handle is NULL");
+    if (!dt_per_member) return fail(e, HV_ERR_ARG, "dt_per_member is NULL");
+    return ens_step(e, dt_per_member, n_long, n_short);
+}
+
+int hv_ens_state_read(hv_ens_t e, int32_t member, int32_t field, double *host_out)
+{
+    if (!e) return fail(nullptr, HV_ERR_ARG, "handle is NULL");
+    return member_read(e, member, field, host_out);
+}
+
+int hv_ens_mass(hv_ens_t e, int32_t member, double *mass_out, double *energy_out)
+{
+    if (!e) return fail(nullptr, HV_ERR_ARG, "handle is NULL");
+    return member_mass(e, member, mass_out, energy_out);
+}
+
+int hv_ens_tune(hv_ens_t e, int32_t *tile_x_out, int32_t *ngroups_out)
+{
+    if (!e) return fail(nullptr, HV_ERR_ARG, "handle is NULL");
+    return tune(e, tile_x_out, ngroups_out);
+}
+
+int hv_ens_trace(hv_ens_t e, int32_t on)
+{
+    if (!e) return fail(nullptr, HV_ERR_ARG, "handle is NULL");
+    return trace_on(e, on);
+}
+
+int hv_ens_trace_read(hv_ens_t e, int32_t kind, double *ms_total, int64_t *launches)
+{
+    if (!e) return fail(nullptr, HV_ERR_ARG, "handle is NULL");
+    return trace_read(e, kind, ms_total, launches);
+}
+
+void hv_ens_destroy(hv_ens_t e) { delete e; }
+
+const char *hv_ens_last_error(hv_ens_t e) { return e ? e->err.c_str() : g_global_error.c_str(); }
 
 }  // extern "C"

@@ -25,7 +25,10 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "mixed": MIXED}
 LAYOUTS = {"ijk": IJK, "kij": KIJ}
 
 EXPORTS = ("hv_workspace_bytes", "hv_grid_create", "hv_state_init", "hv_step", "hv_state_read",
-           "hv_mass", "hv_trace", "hv_trace_read", "hv_grid_destroy", "hv_last_error")
+           "hv_mass", "hv_tune", "hv_trace", "hv_trace_read", "hv_grid_destroy", "hv_last_error",
+           "hv_ens_workspace_bytes", "hv_ens_create", "hv_ens_state_init", "hv_ens_step",
+           "hv_ens_state_read", "hv_ens_mass", "hv_ens_tune", "hv_ens_trace", "hv_ens_trace_read",
+           "hv_ens_destroy", "hv_ens_last_error")
 K_SLOW_PREP, K_SLOW_FLUX, K_SHORT_STEP, K_MASS = 0, 1, 2, 3
 KERNEL_KINDS = {"slow_prep": K_SLOW_PREP, "slow_flux": K_SLOW_FLUX, "short_step": K_SHORT_STEP,
                 "mass": K_MASS}
@@ -77,6 +80,34 @@ def load():
     L.hv_trace_read.restype = ctypes.c_int
     L.hv_trace_read.argtypes = [ctypes.c_void_p, ctypes.c_int32, _dp,
                                 ctypes.POINTER(ctypes.c_int64)]
+    L.hv_tune.restype = ctypes.c_int
+    L.hv_tune.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]
+    L.hv_ens_workspace_bytes.restype = ctypes.c_size_t
+    L.hv_ens_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.POINTER(GridDesc)]
+    L.hv_ens_create.restype = ctypes.c_int
+    L.hv_ens_create.argtypes = [ctypes.c_int32, ctypes.POINTER(GridDesc), ctypes.c_void_p,
+                                ctypes.c_size_t, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+    L.hv_ens_state_init.restype = ctypes.c_int
+    L.hv_ens_state_init.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(_dp), _dp, _dp,
+                                    _dp]
+    L.hv_ens_step.restype = ctypes.c_int
+    L.hv_ens_step.argtypes = [ctypes.c_void_p, _dp, ctypes.c_int32, ctypes.c_int32]
+    L.hv_ens_state_read.restype = ctypes.c_int
+    L.hv_ens_state_read.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, _dp]
+    L.hv_ens_mass.restype = ctypes.c_int
+    L.hv_ens_mass.argtypes = [ctypes.c_void_p, ctypes.c_int32, _dp, _dp]
+    L.hv_ens_tune.restype = ctypes.c_int
+    L.hv_ens_tune.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                              ctypes.POINTER(ctypes.c_int32)]
+    L.hv_ens_trace.restype = ctypes.c_int
+    L.hv_ens_trace.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    L.hv_ens_trace_read.restype = ctypes.c_int
+    L.hv_ens_trace_read.argtypes = [ctypes.c_void_p, ctypes.c_int32, _dp,
+                                    ctypes.POINTER(ctypes.c_int64)]
+    L.hv_ens_destroy.restype = None
+    L.hv_ens_destroy.argtypes = [ctypes.c_void_p]
+    L.hv_ens_last_error.restype = ctypes.c_char_p
+    L.hv_ens_last_error.argtypes = [ctypes.c_void_p]
     L.hv_grid_destroy.restype = None
     L.hv_grid_destroy.argtypes = [ctypes.c_void_p]
     L.hv_last_error.restype = ctypes.c_char_p
@@ -164,6 +195,13 @@ class Domain:
                                    ctypes.byref(e) if energy else None))
         return (m.value, e.value) if energy else m.value
 
+    def tune(self):
+        """Autotune the tile shapes; returns the chosen x-extent per kernel kind
+        (slow prep, slow flux, short step)."""
+        out = (ctypes.c_int32 * 3)()
+        self._check(load().hv_tune(self.handle, out))
+        return list(out)
+
     def trace(self, on: bool):
         return self._check(load().hv_trace(self.handle, 1 if on else 0))
 
@@ -180,6 +218,113 @@ class Domain:
     def close(self):
         if getattr(self, "handle", None):
             load().hv_grid_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ptrs5(fields):
+    arrs = [np.ascontiguousarray(f, dtype=np.float64) for f in fields]
+    return arrs, (_dp * 5)(*[a.ctypes.data_as(_dp) for a in arrs])
+
+
+class Ensemble:
+    """Independent domains of uneven sizes advanced together (hv_ens_*).
+
+    ``states``: sequence of objects like the ones Domain takes.  All members
+    share precision and layout; each keeps its own dt (``state.dt``).
+    """
+
+    def __init__(self, states, precision="fp32", layout="kij", device="cuda", stream=None,
+                 init=True):
+        import torch
+        L = load()
+        self.n = len(states)
+        self.shapes = [(int(s.nz), int(s.ny), int(s.nx)) for s in states]
+        self._zfs = [np.ascontiguousarray(s.zf, dtype=np.float64) for s in states]
+        descs = (GridDesc * self.n)()
+        for q, s in enumerate(states):
+            descs[q] = GridDesc(int(s.nx), int(s.ny), int(s.nz), float(s.dx), float(s.dy),
+                                self._zfs[q].ctypes.data_as(_dp), None,
+                                PRECISIONS[precision] if isinstance(precision, str) else int(precision),
+                                LAYOUTS[layout] if isinstance(layout, str) else int(layout),
+                                float(getattr(s, "beta", 0.55)), 0.0)
+        self._descs = descs
+        nbytes = int(L.hv_ens_workspace_bytes(self.n, descs))
+        if nbytes == 0:
+            raise HvError(HV_ERR_ARG, L.hv_ens_last_error(None).decode())
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
+        h = ctypes.c_void_p()
+        rc = L.hv_ens_create(self.n, descs, ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                             ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if rc != HV_OK:
+            raise HvError(rc, L.hv_ens_last_error(None).decode())
+        self.handle = h
+        self.dts = np.array([float(getattr(s, "dt", 10.0)) for s in states])
+        if init:
+            for q, s in enumerate(states):
+                self.init(q, s.fields, s.rho_ref, s.rt_ref, s.p_ref)
+
+    def _check(self, rc):
+        if rc != HV_OK:
+            raise HvError(rc, load().hv_ens_last_error(self.handle).decode())
+        return rc
+
+    def init(self, member, fields, rho_ref, rt_ref, p_ref):
+        keep, ptrs = _ptrs5(fields)
+        refs = [np.ascontiguousarray(r, dtype=np.float64) for r in (rho_ref, rt_ref, p_ref)]
+        return self._check(load().hv_ens_state_init(self.handle, int(member), ptrs,
+                                                    *[r.ctypes.data_as(_dp) for r in refs]))
+
+    def step(self, n_long: int, n_short: int, dts=None):
+        d = np.ascontiguousarray(self.dts if dts is None else dts, dtype=np.float64)
+        return self._check(load().hv_ens_step(self.handle, d.ctypes.data_as(_dp), int(n_long),
+                                              int(n_short)))
+
+    def read(self, member: int, field: int) -> np.ndarray:
+        nz, ny, nx = self.shapes[member]
+        out = np.empty((nz + 1 if field == RHOW else nz, ny, nx), dtype=np.float64)
+        self._check(load().hv_ens_state_read(self.handle, int(member), int(field),
+                                             out.ctypes.data_as(_dp)))
+        return out
+
+    def read_all(self, member: int):
+        return [self.read(member, f) for f in range(5)]
+
+    def mass(self, member: int, energy: bool = False):
+        m = ctypes.c_double()
+        e = ctypes.c_double()
+        self._check(load().hv_ens_mass(self.handle, int(member), ctypes.byref(m),
+                                       ctypes.byref(e) if energy else None))
+        return (m.value, e.value) if energy else m.value
+
+    def tune(self):
+        out = (ctypes.c_int32 * 9)()
+        ng = ctypes.c_int32()
+        self._check(load().hv_ens_tune(self.handle, out, ctypes.byref(ng)))
+        return [list(out[3 * g:3 * g + 3]) for g in range(ng.value)]
+
+    def trace(self, on: bool):
+        return self._check(load().hv_ens_trace(self.handle, 1 if on else 0))
+
+    def trace_read(self):
+        out = {}
+        for name, kind in KERNEL_KINDS.items():
+            ms = ctypes.c_double()
+            n = ctypes.c_int64()
+            self._check(load().hv_ens_trace_read(self.handle, kind, ctypes.byref(ms),
+                                                 ctypes.byref(n)))
+            out[name] = (ms.value, n.value)
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().hv_ens_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

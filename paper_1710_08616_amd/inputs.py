@@ -268,6 +268,40 @@ def rest_state(nx, ny, nz, dx=2000.0, dy=2000.0, zf=None, reference="isothermal"
 # --------------------------------------------------------------------------
 # named workloads
 # --------------------------------------------------------------------------
+C_SOUND = 347.2   # acoustic speed of the isothermal 300 K reference (m/s)
+
+
+def ensemble_dt(dx: float, dy: float, u_bg: float, n_short: int = 6,
+                courant: float = 0.8, cap: float = 10.0) -> float:
+    """Long step keeping the horizontal acoustic Courant number of the short
+    step below ``courant``: min(cap, floor to 0.25 s of
+    courant * n / ((c_s + |u_bg| + 1) * sqrt(1/dx^2 + 1/dy^2)))."""
+    raw = courant * n_short / ((C_SOUND + abs(u_bg) + 1.0) * math.sqrt(1.0 / dx ** 2 + 1.0 / dy ** 2))
+    return min(cap, math.floor(raw / 0.25) * 0.25)
+
+
+def ensemble(count: int = 48, seed: int = 1713, nmin: int = 128, nmax: int = 512,
+             nzs=(32, 64), n_short: int = 6, n_long: int = 20) -> List[State]:
+    """Independent members of uneven sizes, each drawn from its own seed
+    seed*1000 + m: nx, ny ~ U{nmin..nmax}, nz from ``nzs``, dx = dy ~ U[1, 4] km,
+    u_bg ~ U[0, 30] m/s, one bubble (r = 4 km at 5 km, random x, y) and noise."""
+    out = []
+    for m in range(count):
+        ms = seed * 1000 + m
+        rng = np.random.default_rng(ms)
+        nx = int(rng.integers(nmin, nmax + 1))
+        ny = int(rng.integers(nmin, nmax + 1))
+        nz = int(nzs[int(rng.integers(0, len(nzs)))])
+        dx = float(rng.uniform(1000.0, 4000.0))
+        u_bg = float(rng.uniform(0.0, 30.0))
+        xb, yb = float(rng.uniform(0.0, nx * dx)), float(rng.uniform(0.0, ny * dx))
+        dt = ensemble_dt(dx, dx, u_bg, n_short)
+        out.append(make_state(nx, ny, nz, dx=dx, dy=dx, seed=ms, bubbles=[(xb, yb, 5000.0, 4000.0)],
+                              u_bg=u_bg, dt=dt, n_short=n_short, n_long=n_long,
+                              name=f"member{m}"))
+    return out
+
+
 def workload(name: str) -> State:
     """The synthetic single-domain workloads used by tests and the benchmark.
 

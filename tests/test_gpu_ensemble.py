@@ -1,0 +1,133 @@
+"""GPU tests of the batched ensemble (hv_ens_*) and of the launch machinery
+shared with the single grid: hipGraph replay, autotuned tile shapes.
+
+Every cell's arithmetic is fixed, so the results must be bitwise identical
+whether a domain runs alone or inside an ensemble, with any tile shape, and
+with graph replay or direct launches.
+"""
+import numpy as np
+import pytest
+
+from paper_1710_08616_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hv():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1710_08616_amd import hevi
+    hevi.load()
+    return hevi
+
+
+def _members():
+    a = inputs.make_state(20, 13, 32, seed=5, dt=8.0, n_short=4, noise=0.3,
+                          bubbles=[(1.5e4, 1e4, 4e3, 6e3)])
+    b = inputs.make_state(24, 16, 64, seed=6, dt=10.0, n_short=4, dx=3000.0, dy=3000.0, u_bg=20.0)
+    c = inputs.make_state(33, 17, 32, seed=7, dt=6.5, n_short=4, dx=1500.0, dy=1500.0, u_bg=3.0)
+    d = inputs.make_state(16, 40, 64, seed=8, dt=9.0, n_short=4, noise=0.5)
+    return [a, b, c, d]
+
+
+def _alone(hv, s, prec, n_long, n_short):
+    d = hv.Domain(s, precision=prec)
+    d.step(s.dt, n_long, n_short)
+    out = d.read_all()
+    d.close()
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "fp32"])
+def test_members_match_the_same_domain_run_alone(hv, prec):
+    ms = _members()
+    print(f"case: ensemble of 4 vs alone, {prec}", flush=True)
+    e = hv.Ensemble(ms, precision=prec)
+    e.step(3, 4)
+    for q, s in enumerate(ms):
+        got = e.read_all(q)
+        ref = _alone(hv, s, prec, 3, 4)
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b), (q, prec)
+    e.close()
+
+
+def test_fp64_member_matches_oracle(hv, oracle):
+    ms = _members()
+    print("case: ensemble fp64 vs oracle", flush=True)
+    e = hv.Ensemble(ms, precision="fp64")
+    e.step(2, 4)
+    for q in (1, 2):
+        ref = oracle.step(ms[q], n_long=2, n_short=4)
+        for name, a, b in zip(inputs.FIELD_NAMES, e.read_all(q), ref):
+            err = np.abs(a - b).max() / np.ptp(b)
+            assert err <= 1e-11, (q, name, err)
+    e.close()
+
+
+def test_tuned_tile_shapes_give_identical_results(hv, tmp_path, monkeypatch):
+    monkeypatch.setenv("HV_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    ms = _members()
+    print("case: ensemble tuned vs untuned", flush=True)
+    e0 = hv.Ensemble(ms, precision="fp32")
+    e0.step(2, 4)
+    ref = [e0.read_all(q) for q in range(len(ms))]
+    e0.close()
+    e1 = hv.Ensemble(ms, precision="fp32")
+    shapes = e1.tune()
+    assert len(shapes) == 2 and all(x in (16, 8, 4) for g in shapes for x in g)
+    e1.step(2, 4)
+    for q in range(len(ms)):
+        for a, b in zip(e1.read_all(q), ref[q]):
+            assert np.array_equal(a, b)
+    e1.close()
+    assert (tmp_path / "tune.txt").exists()
+
+
+def test_graph_replay_equals_direct_launches(hv):
+    s = inputs.workload("small")
+    print("case: graph vs direct launches", flush=True)
+    a = hv.Domain(s, precision="fp32")
+    a.step(s.dt, 3, s.n_short)          # graph replay
+    b = hv.Domain(s, precision="fp32")
+    b.trace(True)                         # direct launches with events
+    b.step(s.dt, 3, s.n_short)
+    kern = b.trace_read()
+    b.trace(False)
+    assert kern["short_step"][1] == 3 * 3 * s.n_short
+    assert kern["slow_prep"][1] == 9 and kern["mass"][1] == 3
+    for x, y in zip(a.read_all(), b.read_all()):
+        assert np.array_equal(x, y)
+    a.close()
+    b.close()
+
+
+def test_member_mass_is_conserved(hv):
+    ms = _members()
+    e = hv.Ensemble(ms, precision="fp64")
+    m0 = [e.mass(q) for q in range(len(ms))]
+    e.step(4, 4)
+    for q in range(len(ms)):
+        assert abs(e.mass(q) - m0[q]) <= 1e-14 * m0[q]
+    e.close()
+
+
+def test_ensemble_errors(hv):
+    ms = _members()
+    e = hv.Ensemble(ms, precision="fp32", init=False)
+    e.init(0, ms[0].fields, ms[0].rho_ref, ms[0].rt_ref, ms[0].p_ref)
+    with pytest.raises(hv.HvError) as err:
+        e.step(1, 4)
+    assert err.value.code == hv.HV_ERR_STATE
+    buf = np.zeros(64)
+    rc = hv.load().hv_ens_state_read(e.handle, 7, 0,
+                                     buf.ctypes.data_as(hv.ctypes.POINTER(hv.ctypes.c_double)))
+    assert rc == hv.HV_ERR_ARG
+    for q in range(1, len(ms)):
+        e.init(q, ms[q].fields, ms[q].rho_ref, ms[q].rt_ref, ms[q].p_ref)
+    with pytest.raises(hv.HvError) as err:
+        e.step(1, 4, dts=[10.0, -1.0, 1.0, 1.0])
+    assert err.value.code == hv.HV_ERR_ARG
+    e.step(1, 4)
+    e.close()

@@ -32,6 +32,18 @@
  *    from the state at the start of the long step, with the slow tendencies
  *    evaluated on the previous stage's result.
  *  - EOS p = P00 (R Theta / P00)^gamma; gamma = 1.4, g = 9.80665 (SI).
+ *  - Terrain (optional): terrain-following height z = zeta + h (1 - zeta/H)
+ *    (Gal-Chen & Somerville 1975).  J = 1 - h/H per column; horizontal mass
+ *    fluxes carry J (two-point means on faces), and the momentum control
+ *    volumes take means of those cell-face mass fluxes; the flux through zeta
+ *    surfaces is Omega = W - (1 - zeta/H) * (slope-weighted U and V, averaged
+ *    to the level face), zero on both lids; divergences are divided by J;
+ *    the horizontal pressure gradient gains + (z_x/J) * (mean of d p'/d zeta
+ *    of the two columns; one-sided at the lowest and highest cells); in the
+ *    vertical part dz becomes J dz and W* becomes Omega* = beta W+ +
+ *    (1 - beta) W - E, with E the slope term of Omega evaluated with the new
+ *    horizontal momentum.  The reference state is then given at every cell's true height.
+ *    W is held at 0 on both lids (the lower boundary condition is Omega = 0).
  *
  * Pins (tests that hold this file to something other than itself): the
  * Koren limiter table and its smooth-regime closed form; the exact
@@ -70,10 +82,26 @@ typedef struct {
     double beta;              /* off-centring of the vertical coupling       */
     double grav;              /* gravitational acceleration                   */
     const double *zf;         /* nz+1 level-face heights, zf[0] = 0           */
-    const double *rho_ref;    /* nz reference density at cell centres         */
-    const double *rt_ref;     /* nz reference rho*theta                       */
-    const double *p_ref;      /* nz reference pressure                        */
+    const double *rho_ref;    /* reference density at cell centres: nz values,
+                                 or nx*ny*nz with terrain                     */
+    const double *rt_ref;     /* reference rho*theta, same shape              */
+    const double *p_ref;      /* reference pressure, same shape               */
+    const double *terrain;    /* nx*ny surface heights, NULL = flat           */
 } or_grid;
+
+/* index of the reference value of cell c (level k) */
+static inline size_t RI(const or_grid *g, size_t c, int k) { return g->terrain ? c : (size_t)k; }
+
+/* horizontal geometry: Jacobians and terrain slopes (flat: 1 and 0) */
+typedef struct {
+    double *J;    /* nx*ny  J = 1 - h/H of column (i, j)                      */
+    double *Ju;   /* nx*ny  J on the west x-face of column (i, j)             */
+    double *Jv;   /* nx*ny  J on the south y-face                             */
+    double *su;   /* nx*ny  dh/dx on the west x-face                          */
+    double *sv;   /* nx*ny  dh/dy on the south y-face                         */
+    double *dc;   /* nz     1 - zeta/H at cell centres                        */
+    double *df;   /* nz+1   1 - zeta/H at level faces                         */
+} or_geo;
 
 /* vertical metrics derived from the face heights */
 typedef struct {
@@ -117,6 +145,47 @@ static inline int clampi(int i, int lo, int hi)
 {
     return i < lo ? lo : (i > hi ? hi : i);
 }
+
+static void geo_free(or_geo *q)
+{
+    free(q->J); free(q->Ju); free(q->Jv); free(q->su); free(q->sv); free(q->dc); free(q->df);
+}
+
+static int geo_init(const or_grid *g, or_geo *q)
+{
+    const int nx = g->nx, ny = g->ny, nz = g->nz;
+    const size_t nxy = (size_t)nx * ny;
+    const double H = g->zf[nz];
+    q->J = (double *)malloc(nxy * sizeof(double));
+    q->Ju = (double *)malloc(nxy * sizeof(double));
+    q->Jv = (double *)malloc(nxy * sizeof(double));
+    q->su = (double *)malloc(nxy * sizeof(double));
+    q->sv = (double *)malloc(nxy * sizeof(double));
+    q->dc = (double *)malloc((size_t)nz * sizeof(double));
+    q->df = (double *)malloc(((size_t)nz + 1) * sizeof(double));
+    if (!q->J || !q->Ju || !q->Jv || !q->su || !q->sv || !q->dc || !q->df) return OR_ENOMEM;
+    for (int k = 0; k < nz; ++k) q->dc[k] = 1.0 - 0.5 * (g->zf[k] + g->zf[k + 1]) / H;
+    for (int k = 0; k <= nz; ++k) q->df[k] = 1.0 - g->zf[k] / H;
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            size_t c = (size_t)j * nx + i;
+            if (!g->terrain) {
+                q->J[c] = q->Ju[c] = q->Jv[c] = 1.0;
+                q->su[c] = q->sv[c] = 0.0;
+                continue;
+            }
+            const double h = g->terrain[c];
+            const double hw = g->terrain[(size_t)j * nx + wrapi(i - 1, nx)];
+            const double hs = g->terrain[(size_t)wrapi(j - 1, ny) * nx + i];
+            q->J[c] = 1.0 - h / H;
+            q->Ju[c] = 0.5 * ((1.0 - hw / H) + (1.0 - h / H));
+            q->Jv[c] = 0.5 * ((1.0 - hs / H) + (1.0 - h / H));
+            q->su[c] = (h - hw) / g->dx;
+            q->sv[c] = (h - hs) / g->dy;
+        }
+    return OR_OK;
+}
+
 
 /* ------------------------------------------------------------------------
  * Koren limiter.  With D- = q_L - q_LL (upwind difference) and
@@ -215,24 +284,31 @@ int or_slow_sweep(const or_grid *g, const double *const st[5], double *const out
     const size_t nxy = (size_t)nx * ny, n = nxy * nz, nw = nxy * (nz + 1);
     const double *rp = st[0], *U = st[1], *V = st[2], *W = st[3], *tp = st[4];
     or_vmet vm;
-    if (vmet_init(g, &vm) != OR_OK) { vmet_free(&vm); return OR_ENOMEM; }
+    or_geo geo;
+    memset(&geo, 0, sizeof geo);
+    if (vmet_init(g, &vm) != OR_OK || geo_init(g, &geo) != OR_OK) {
+        vmet_free(&vm); geo_free(&geo);
+        return OR_ENOMEM;
+    }
     double *rho = (double *)malloc(n * sizeof(double));
     double *th = (double *)malloc(n * sizeof(double));
     double *uu = (double *)malloc(n * sizeof(double));
     double *vv = (double *)malloc(n * sizeof(double));
     double *ww = (double *)malloc(nw * sizeof(double));
-    if (!rho || !th || !uu || !vv || !ww) {
-        free(rho); free(th); free(uu); free(vv); free(ww); vmet_free(&vm);
+    double *om = (double *)malloc(nw * sizeof(double));
+    if (!rho || !th || !uu || !vv || !ww || !om) {
+        free(rho); free(th); free(uu); free(vv); free(ww); free(om); vmet_free(&vm); geo_free(&geo);
         return OR_ENOMEM;
     }
+#define C2(i, j) ((size_t)(j) * (size_t)nx + (size_t)(i))
     /* full density, theta, and the advected specific velocities */
 #pragma omp parallel for schedule(static)
     for (int jk = 0; jk < ny * nz; ++jk) {
         int j = jk % ny, k = jk / ny;
         for (int i = 0; i < nx; ++i) {
             size_t c = C3(i, j, k);
-            rho[c] = g->rho_ref[k] + rp[c];
-            th[c] = (g->rt_ref[k] + tp[c]) / rho[c];
+            rho[c] = g->rho_ref[RI(g, c, k)] + rp[c];
+            th[c] = (g->rt_ref[RI(g, c, k)] + tp[c]) / rho[c];
         }
     }
 #pragma omp parallel for schedule(static)
@@ -244,13 +320,28 @@ int or_slow_sweep(const or_grid *g, const double *const st[5], double *const out
             vv[c] = V[c] / (0.5 * (rho[C3(i, wrapi(j - 1, ny), k)] + rho[c]));
         }
     }
+    /* w on level faces, and the mass flux through the zeta surfaces:
+     * Omega = W - (1 - zeta/H) * (slope-weighted U and V at the face), with
+     * the slope-weighted momenta averaged to the column centre and then
+     * interpolated linearly in z to the face; Omega = 0 on both lids. */
 #pragma omp parallel for schedule(static)
     for (int jk = 0; jk < ny * (nz + 1); ++jk) {
         int j = jk % ny, k = jk / ny;
         for (int i = 0; i < nx; ++i) {
             size_t c = C3(i, j, k);
-            if (k == 0 || k == nz) ww[c] = 0.0;
-            else ww[c] = W[c] / (vm.a[k] * rho[C3(i, j, k)] + vm.b[k] * rho[C3(i, j, k - 1)]);
+            if (k == 0 || k == nz) {
+                ww[c] = 0.0;
+                om[c] = 0.0;
+                continue;
+            }
+            ww[c] = W[c] / (vm.a[k] * rho[C3(i, j, k)] + vm.b[k] * rho[C3(i, j, k - 1)]);
+            const double su0 = geo.su[C2(i, j)], su1 = geo.su[C2(wrapi(i + 1, nx), j)];
+            const double sv0 = geo.sv[C2(i, j)], sv1 = geo.sv[C2(i, wrapi(j + 1, ny))];
+            const double mxk = 0.5 * (su0 * U[C3(i, j, k)] + su1 * U[C3(wrapi(i + 1, nx), j, k)]);
+            const double mxm = 0.5 * (su0 * U[C3(i, j, k - 1)] + su1 * U[C3(wrapi(i + 1, nx), j, k - 1)]);
+            const double myk = 0.5 * (sv0 * V[C3(i, j, k)] + sv1 * V[C3(i, wrapi(j + 1, ny), k)]);
+            const double mym = 0.5 * (sv0 * V[C3(i, j, k - 1)] + sv1 * V[C3(i, wrapi(j + 1, ny), k - 1)]);
+            om[c] = W[c] - geo.df[k] * ((vm.a[k] * mxk + vm.b[k] * mxm) + (vm.a[k] * myk + vm.b[k] * mym));
         }
     }
 
@@ -269,12 +360,14 @@ int or_slow_sweep(const or_grid *g, const double *const st[5], double *const out
             double fx[2], fy[2], fz[2];
             for (int s = 0; s < 2; ++s) {
                 int cc = i - 1 + s;                   /* centre of cell cc */
-                double m = 0.5 * (U[C3(wrapi(cc, nx), j, k)] + U[C3(wrapi(cc + 1, nx), j, k)]);
+                double m = 0.5 * (geo.Ju[C2(wrapi(cc, nx), j)] * U[C3(wrapi(cc, nx), j, k)] +
+                                  geo.Ju[C2(wrapi(cc + 1, nx), j)] * U[C3(wrapi(cc + 1, nx), j, k)]);
                 fx[s] = m * or_face(uu[C3(wrapi(cc - 1, nx), j, k)], uu[C3(wrapi(cc, nx), j, k)],
                                     uu[C3(wrapi(cc + 1, nx), j, k)], uu[C3(wrapi(cc + 2, nx), j, k)],
                                     m, LIM);
                 int jf = j + s;                       /* corner (face i, face jf) */
-                m = 0.5 * (V[C3(wrapi(i - 1, nx), wrapi(jf, ny), k)] + V[C3(i, wrapi(jf, ny), k)]);
+                m = 0.5 * (geo.Jv[C2(wrapi(i - 1, nx), wrapi(jf, ny))] * V[C3(wrapi(i - 1, nx), wrapi(jf, ny), k)] +
+                           geo.Jv[C2(i, wrapi(jf, ny))] * V[C3(i, wrapi(jf, ny), k)]);
                 fy[s] = m * or_face(uu[C3(i, wrapi(jf - 2, ny), k)], uu[C3(i, wrapi(jf - 1, ny), k)],
                                     uu[C3(i, wrapi(jf, ny), k)], uu[C3(i, wrapi(jf + 1, ny), k)],
                                     m, LIM);
@@ -282,23 +375,26 @@ int or_slow_sweep(const or_grid *g, const double *const st[5], double *const out
                 if (kf == 0 || kf == nz) {
                     fz[s] = 0.0;
                 } else {
-                    m = 0.5 * (W[C3(wrapi(i - 1, nx), j, kf)] + W[C3(i, j, kf)]);
+                    m = 0.5 * (om[C3(wrapi(i - 1, nx), j, kf)] + om[C3(i, j, kf)]);
                     fz[s] = m * or_face(uu[C3(i, j, clampi(kf - 2, 0, nz - 1))], uu[C3(i, j, kf - 1)],
                                         uu[C3(i, j, kf)], uu[C3(i, j, clampi(kf + 1, 0, nz - 1))],
                                         m, LIM);
                 }
             }
-            SU[c] = -((fx[1] - fx[0]) / dx + (fy[1] - fy[0]) / dy + (fz[1] - fz[0]) / vm.dz[k]);
+            SU[c] = -((fx[1] - fx[0]) / dx + (fy[1] - fy[0]) / dy + (fz[1] - fz[0]) / vm.dz[k]) /
+                    geo.Ju[C2(i, j)];
 
             /* ---- y-momentum at the south face of cell j ---- */
             for (int s = 0; s < 2; ++s) {
                 int iff = i + s;                      /* corner (face iff, face j) */
-                double m = 0.5 * (U[C3(wrapi(iff, nx), wrapi(j - 1, ny), k)] + U[C3(wrapi(iff, nx), j, k)]);
+                double m = 0.5 * (geo.Ju[C2(wrapi(iff, nx), wrapi(j - 1, ny))] * U[C3(wrapi(iff, nx), wrapi(j - 1, ny), k)] +
+                                  geo.Ju[C2(wrapi(iff, nx), j)] * U[C3(wrapi(iff, nx), j, k)]);
                 fx[s] = m * or_face(vv[C3(wrapi(iff - 2, nx), j, k)], vv[C3(wrapi(iff - 1, nx), j, k)],
                                     vv[C3(wrapi(iff, nx), j, k)], vv[C3(wrapi(iff + 1, nx), j, k)],
                                     m, LIM);
                 int cc = j - 1 + s;                   /* centre of cell cc */
-                m = 0.5 * (V[C3(i, wrapi(cc, ny), k)] + V[C3(i, wrapi(cc + 1, ny), k)]);
+                m = 0.5 * (geo.Jv[C2(i, wrapi(cc, ny))] * V[C3(i, wrapi(cc, ny), k)] +
+                           geo.Jv[C2(i, wrapi(cc + 1, ny))] * V[C3(i, wrapi(cc + 1, ny), k)]);
                 fy[s] = m * or_face(vv[C3(i, wrapi(cc - 1, ny), k)], vv[C3(i, wrapi(cc, ny), k)],
                                     vv[C3(i, wrapi(cc + 1, ny), k)], vv[C3(i, wrapi(cc + 2, ny), k)],
                                     m, LIM);
@@ -306,25 +402,26 @@ int or_slow_sweep(const or_grid *g, const double *const st[5], double *const out
                 if (kf == 0 || kf == nz) {
                     fz[s] = 0.0;
                 } else {
-                    m = 0.5 * (W[C3(i, wrapi(j - 1, ny), kf)] + W[C3(i, j, kf)]);
+                    m = 0.5 * (om[C3(i, wrapi(j - 1, ny), kf)] + om[C3(i, j, kf)]);
                     fz[s] = m * or_face(vv[C3(i, j, clampi(kf - 2, 0, nz - 1))], vv[C3(i, j, kf - 1)],
                                         vv[C3(i, j, kf)], vv[C3(i, j, clampi(kf + 1, 0, nz - 1))],
                                         m, LIM);
                 }
             }
-            SV[c] = -((fx[1] - fx[0]) / dx + (fy[1] - fy[0]) / dy + (fz[1] - fz[0]) / vm.dz[k]);
+            SV[c] = -((fx[1] - fx[0]) / dx + (fy[1] - fy[0]) / dy + (fz[1] - fz[0]) / vm.dz[k]) /
+                    geo.Jv[C2(i, j)];
 
             /* ---- Theta residual: limited minus centred face theta ---- */
             for (int s = 0; s < 2; ++s) {
                 int f = i + s;
-                double m = U[C3(wrapi(f, nx), j, k)];
+                double m = geo.Ju[C2(wrapi(f, nx), j)] * U[C3(wrapi(f, nx), j, k)];
                 double tl = or_face(th[C3(wrapi(f - 2, nx), j, k)], th[C3(wrapi(f - 1, nx), j, k)],
                                     th[C3(wrapi(f, nx), j, k)], th[C3(wrapi(f + 1, nx), j, k)],
                                     m, LIM);
                 double tcen = 0.5 * (th[C3(wrapi(f - 1, nx), j, k)] + th[C3(wrapi(f, nx), j, k)]);
                 fx[s] = m * (tl - tcen);
                 int h = j + s;
-                m = V[C3(i, wrapi(h, ny), k)];
+                m = geo.Jv[C2(i, wrapi(h, ny))] * V[C3(i, wrapi(h, ny), k)];
                 tl = or_face(th[C3(i, wrapi(h - 2, ny), k)], th[C3(i, wrapi(h - 1, ny), k)],
                              th[C3(i, wrapi(h, ny), k)], th[C3(i, wrapi(h + 1, ny), k)], m, LIM);
                 tcen = 0.5 * (th[C3(i, wrapi(h - 1, ny), k)] + th[C3(i, wrapi(h, ny), k)]);
@@ -333,18 +430,20 @@ int or_slow_sweep(const or_grid *g, const double *const st[5], double *const out
                 if (kf == 0 || kf == nz) {
                     fz[s] = 0.0;
                 } else {
-                    m = W[C3(i, j, kf)];
+                    m = om[C3(i, j, kf)];
                     tl = or_face(th[C3(i, j, clampi(kf - 2, 0, nz - 1))], th[C3(i, j, kf - 1)],
                                  th[C3(i, j, kf)], th[C3(i, j, clampi(kf + 1, 0, nz - 1))], m, LIM);
                     tcen = vm.a[kf] * th[C3(i, j, kf)] + vm.b[kf] * th[C3(i, j, kf - 1)];
                     fz[s] = m * (tl - tcen);
                 }
             }
-            RT[c] = -((fx[1] - fx[0]) / dx + (fy[1] - fy[0]) / dy + (fz[1] - fz[0]) / vm.dz[k]);
+            RT[c] = -((fx[1] - fx[0]) / dx + (fy[1] - fy[0]) / dy + (fz[1] - fz[0]) / vm.dz[k]) /
+                    geo.J[C2(i, j)];
 
             /* ---- stage coefficients ---- */
-            double pps = g->p_ref[k] * expm1(OR_GAMMA * log1p(tp[c] / g->rt_ref[k]));
-            double cs = OR_GAMMA * (g->p_ref[k] + pps) / (g->rt_ref[k] + tp[c]);
+            const size_t r = RI(g, c, k);
+            double pps = g->p_ref[r] * expm1(OR_GAMMA * log1p(tp[c] / g->rt_ref[r]));
+            double cs = OR_GAMMA * (g->p_ref[r] + pps) / (g->rt_ref[r] + tp[c]);
             ths[c] = th[c];
             Cs[c] = cs;
             P0[c] = pps - cs * tp[c];
@@ -361,26 +460,31 @@ int or_slow_sweep(const or_grid *g, const double *const st[5], double *const out
             double fx[2], fy[2], fz[2];
             for (int s = 0; s < 2; ++s) {
                 int iff = i + s;                      /* edge (x-face iff, level face k) */
-                double m = 0.5 * (U[C3(wrapi(iff, nx), j, k - 1)] + U[C3(wrapi(iff, nx), j, k)]);
+                double ju = geo.Ju[C2(wrapi(iff, nx), j)];
+                double m = 0.5 * (ju * U[C3(wrapi(iff, nx), j, k - 1)] + ju * U[C3(wrapi(iff, nx), j, k)]);
                 fx[s] = m * or_face(ww[C3(wrapi(iff - 2, nx), j, k)], ww[C3(wrapi(iff - 1, nx), j, k)],
                                     ww[C3(wrapi(iff, nx), j, k)], ww[C3(wrapi(iff + 1, nx), j, k)],
                                     m, LIM);
                 int jf = j + s;
-                m = 0.5 * (V[C3(i, wrapi(jf, ny), k - 1)] + V[C3(i, wrapi(jf, ny), k)]);
+                double jv = geo.Jv[C2(i, wrapi(jf, ny))];
+                m = 0.5 * (jv * V[C3(i, wrapi(jf, ny), k - 1)] + jv * V[C3(i, wrapi(jf, ny), k)]);
                 fy[s] = m * or_face(ww[C3(i, wrapi(jf - 2, ny), k)], ww[C3(i, wrapi(jf - 1, ny), k)],
                                     ww[C3(i, wrapi(jf, ny), k)], ww[C3(i, wrapi(jf + 1, ny), k)],
                                     m, LIM);
                 int cc = k - 1 + s;                   /* centre of cell cc */
-                m = 0.5 * (W[C3(i, j, cc)] + W[C3(i, j, cc + 1)]);
+                m = 0.5 * (om[C3(i, j, cc)] + om[C3(i, j, cc + 1)]);
                 fz[s] = m * or_face(ww[C3(i, j, clampi(cc - 1, 0, nz))], ww[C3(i, j, cc)],
                                     ww[C3(i, j, cc + 1)], ww[C3(i, j, clampi(cc + 2, 0, nz))],
                                     m, LIM);
             }
-            SW[c] = -((fx[1] - fx[0]) / dx + (fy[1] - fy[0]) / dy + (fz[1] - fz[0]) / vm.dzf[k]);
+            SW[c] = -((fx[1] - fx[0]) / dx + (fy[1] - fy[0]) / dy + (fz[1] - fz[0]) / vm.dzf[k]) /
+                    geo.J[C2(i, j)];
         }
     }
-    free(rho); free(th); free(uu); free(vv); free(ww);
+#undef C2
+    free(rho); free(th); free(uu); free(vv); free(ww); free(om);
     vmet_free(&vm);
+    geo_free(&geo);
     return OR_OK;
 }
 
@@ -416,21 +520,24 @@ int or_thomas(int n, const double *a, const double *b, const double *c, const do
  *
  * Inputs per cell m = 0..nz-1: rt (rho' after the horizontal divergence),
  * tt (Theta' after it), rp and pp (rho' and p' at the start of the short
- * step), P0, Cs, ths (stage coefficients); per level face k = 0..nz: W (old)
- * and SW.  With W* = beta W+ + (1-beta) W:
- *   rho'+_m   = rt_m - (dtau/dz_m) (W*_{m+1} - W*_m)
- *   Theta'+_m = tt_m - (dtau/dz_m) (thf_{m+1} W*_{m+1} - thf_m W*_m)
+ * step), P0, Cs, ths (stage coefficients); per level face k = 0..nz: W (old),
+ * SW and E (the terrain-slope part of the flux through the zeta surface,
+ * zero on flat ground).  dz and dzf are the column's own thicknesses
+ * (J dzeta with terrain).  With Omega* = beta W+ + (1-beta) W - E:
+ *   rho'+_m   = rt_m - (dtau/dz_m) (Omega*_{m+1} - Omega*_m)
+ *   Theta'+_m = tt_m - (dtau/dz_m) (thf_{m+1} Omega*_{m+1} - thf_m Omega*_m)
  *   p'+       = P0 + Cs Theta'+
  *   W+_k      = W_k + dtau [ SW_k - (p*_k - p*_{k-1})/dzf_k
  *                            - g (a_k rho*_k + b_k rho*_{k-1}) ]
  * with p* = beta p'+ + (1-beta) p', rho* = beta rho'+ + (1-beta) rho',
- * thf the linear interpolation of ths to the faces, and W+ = 0 on the lids.
- * Substituting the first three lines into the last gives the tridiagonal
- * system assembled by or_vi_assemble for the interior faces k = 1..nz-1.
+ * thf the linear interpolation of ths to the faces, and W+ = Omega* = 0 on
+ * the lids.  Substituting the first three lines into the last gives the
+ * tridiagonal system assembled by or_vi_assemble for the interior faces
+ * k = 1..nz-1.
  * ---------------------------------------------------------------------- */
 typedef struct {
     int nz;
-    const double *dz, *dzf, *a, *b;
+    const double *dz, *dzf, *a, *b, *E;
     double beta, dtau, grav;
 } or_col;
 
@@ -449,11 +556,14 @@ static void col_assemble(const or_col *c, const double *rt, const double *tt, co
 {
     const int nz = c->nz;
     const double be = c->beta, dt = c->dtau, g = c->grav;
+    const double *E = c->E;
     col_thf(c, ths, thf);
     for (int m = 0; m < nz; ++m) {
         /* the state each cell would reach with W+ = 0 */
-        double the = tt[m] - ((1.0 - be) * dt / c->dz[m]) * (thf[m + 1] * W[m + 1] - thf[m] * W[m]);
-        double rhe = rt[m] - ((1.0 - be) * dt / c->dz[m]) * (W[m + 1] - W[m]);
+        double the = tt[m] - ((1.0 - be) * dt / c->dz[m]) * (thf[m + 1] * W[m + 1] - thf[m] * W[m])
+                     + (dt / c->dz[m]) * (thf[m + 1] * E[m + 1] - thf[m] * E[m]);
+        double rhe = rt[m] - ((1.0 - be) * dt / c->dz[m]) * (W[m + 1] - W[m])
+                     + (dt / c->dz[m]) * (E[m + 1] - E[m]);
         pE[m] = be * (P0[m] + Cs[m] * the) + (1.0 - be) * pp[m];
         rEs[m] = be * rhe + (1.0 - be) * rp[m];
     }
@@ -475,9 +585,10 @@ static void col_update(const or_col *c, const double *rt, const double *tt, cons
 {
     const int nz = c->nz;
     const double be = c->beta, dt = c->dtau;
+    const double *E = c->E;
     for (int m = 0; m < nz; ++m) {
-        double wsl = be * Wp[m] + (1.0 - be) * W[m];
-        double wsu = be * Wp[m + 1] + (1.0 - be) * W[m + 1];
+        double wsl = be * Wp[m] + (1.0 - be) * W[m] - E[m];
+        double wsu = be * Wp[m + 1] + (1.0 - be) * W[m + 1] - E[m + 1];
         rpo[m] = rt[m] - (dt / c->dz[m]) * (wsu - wsl);
         tpo[m] = tt[m] - (dt / c->dz[m]) * (thf[m + 1] * wsu - thf[m] * wsl);
     }
@@ -506,20 +617,41 @@ static void col_residual(const or_col *c, const double *rt, const double *tt, co
     }
 }
 
+/* Column set-up of the test entry points below: the column's thicknesses
+ * scaled by its Jacobian jac, and E (NULL: zero).  Returns the scratch of
+ * 6 (nz+1) doubles that holds them and the column temporaries. */
+static double *col_setup(int nz, const or_vmet *vm, double jac, const double *E, or_col *c,
+                         double beta, double dtau, double grav)
+{
+    const size_t np = (size_t)nz + 1;
+    double *tmp = (double *)calloc(6 * np, sizeof(double));
+    if (!tmp) return NULL;
+    double *dz = tmp + 3 * np, *dzf = tmp + 4 * np, *e = tmp + 5 * np;
+    for (int k = 0; k < nz; ++k) dz[k] = jac * vm->dz[k];
+    for (int k = 0; k <= nz; ++k) {
+        dzf[k] = jac * vm->dzf[k];
+        e[k] = (E && k > 0 && k < nz) ? E[k] : 0.0;
+    }
+    c->nz = nz; c->dz = dz; c->dzf = dzf; c->a = vm->a; c->b = vm->b; c->E = e;
+    c->beta = beta; c->dtau = dtau; c->grav = grav;
+    return tmp;
+}
+
 /* Column test entry points.  All arrays follow the column conventions above;
- * A, B, C, D and R have nz+1 entries indexed by face. */
-int or_vi_assemble(int nz, const double *zf, double beta, double dtau, double grav,
-                   const double *rt, const double *tt, const double *rp, const double *pp,
-                   const double *P0, const double *Cs, const double *ths, const double *W,
-                   const double *SW, double *A, double *B, double *C, double *D)
+ * A, B, C, D and R have nz+1 entries indexed by face.  jac is the column's
+ * Jacobian (1 on flat ground); E has nz+1 entries or is NULL (zero). */
+int or_vi_assemble(int nz, const double *zf, double beta, double dtau, double grav, double jac,
+                   const double *E, const double *rt, const double *tt, const double *rp,
+                   const double *pp, const double *P0, const double *Cs, const double *ths,
+                   const double *W, const double *SW, double *A, double *B, double *C, double *D)
 {
     or_grid g;
     memset(&g, 0, sizeof g);
     g.nz = nz; g.zf = zf;
     or_vmet vm;
     if (vmet_init(&g, &vm) != OR_OK) { vmet_free(&vm); return OR_ENOMEM; }
-    or_col c = {nz, vm.dz, vm.dzf, vm.a, vm.b, beta, dtau, grav};
-    double *tmp = (double *)calloc(3 * ((size_t)nz + 1), sizeof(double));
+    or_col c;
+    double *tmp = col_setup(nz, &vm, jac, E, &c, beta, dtau, grav);
     if (!tmp) { vmet_free(&vm); return OR_ENOMEM; }
     col_assemble(&c, rt, tt, rp, pp, P0, Cs, ths, W, SW, A, B, C, D, tmp, tmp + nz + 1,
                  tmp + 2 * (nz + 1));
@@ -530,18 +662,18 @@ int or_vi_assemble(int nz, const double *zf, double beta, double dtau, double gr
     return OR_OK;
 }
 
-int or_vi_residual(int nz, const double *zf, double beta, double dtau, double grav,
-                   const double *rt, const double *tt, const double *rp, const double *pp,
-                   const double *P0, const double *Cs, const double *ths, const double *W,
-                   const double *SW, const double *Wp, double *R)
+int or_vi_residual(int nz, const double *zf, double beta, double dtau, double grav, double jac,
+                   const double *E, const double *rt, const double *tt, const double *rp,
+                   const double *pp, const double *P0, const double *Cs, const double *ths,
+                   const double *W, const double *SW, const double *Wp, double *R)
 {
     or_grid g;
     memset(&g, 0, sizeof g);
     g.nz = nz; g.zf = zf;
     or_vmet vm;
     if (vmet_init(&g, &vm) != OR_OK) { vmet_free(&vm); return OR_ENOMEM; }
-    or_col c = {nz, vm.dz, vm.dzf, vm.a, vm.b, beta, dtau, grav};
-    double *tmp = (double *)calloc(3 * ((size_t)nz + 1), sizeof(double));
+    or_col c;
+    double *tmp = col_setup(nz, &vm, jac, E, &c, beta, dtau, grav);
     if (!tmp) { vmet_free(&vm); return OR_ENOMEM; }
     col_residual(&c, rt, tt, rp, pp, P0, Cs, ths, W, SW, Wp, R, tmp, tmp + nz + 1, tmp + 2 * (nz + 1));
     free(tmp);
@@ -553,8 +685,9 @@ int or_vi_residual(int nz, const double *zf, double beta, double dtau, double gr
  * One short step from st_in to st_out (distinct buffers) with the stage's
  * slow arrays sl = {S_U, S_V, S_W, R_Theta, theta_s, P0_s, C_s}.
  * ---------------------------------------------------------------------- */
-static int short_step(const or_grid *g, const or_vmet *vm, const double *const sl[7],
-                      const double *const in[5], double dtau, double *const out[5], double *pp)
+static int short_step(const or_grid *g, const or_vmet *vm, const or_geo *geo,
+                      const double *const sl[7], const double *const in[5], double dtau,
+                      double *const out[5], double *pp)
 {
     const int nx = g->nx, ny = g->ny, nz = g->nz;
     const size_t nxy = (size_t)nx * ny;
@@ -564,6 +697,7 @@ static int short_step(const or_grid *g, const or_vmet *vm, const double *const s
     double *rpo = out[0], *Uo = out[1], *Vo = out[2], *Wo = out[3], *tpo = out[4];
     const double dx = g->dx, dy = g->dy;
     int bad = 0;
+#define C2(i, j) ((size_t)(j) * (size_t)nx + (size_t)(i))
 
     /* p' of the current Theta' with the stage linearisation */
 #pragma omp parallel for schedule(static)
@@ -574,14 +708,37 @@ static int short_step(const or_grid *g, const or_vmet *vm, const double *const s
             pp[c] = P0[c] + Cs[c] * tp[c];
         }
     }
-    /* horizontally explicit momentum, forward in time */
+    /* horizontally explicit momentum, forward in time.  Over terrain the
+     * gradient along the zeta surface is corrected by (z_x/J) dp'/dzeta,
+     * with dp'/dzeta at a cell centre the mean of the differences over its
+     * two level faces (the one inner face at the lowest and highest cell),
+     * averaged over the two columns of the face. */
 #pragma omp parallel for schedule(static)
     for (int jk = 0; jk < ny * nz; ++jk) {
         int j = jk % ny, k = jk / ny;
         for (int i = 0; i < nx; ++i) {
             size_t c = C3(i, j, k);
-            Uo[c] = U[c] + dtau * (SU[c] - (pp[c] - pp[C3(wrapi(i - 1, nx), j, k)]) / dx);
-            Vo[c] = V[c] + dtau * (SV[c] - (pp[c] - pp[C3(i, wrapi(j - 1, ny), k)]) / dy);
+            double corr_x = 0.0, corr_y = 0.0;
+            if (g->terrain) {
+                double gz[3];
+                const int ci[3] = {i, wrapi(i - 1, nx), i};
+                const int cj[3] = {j, j, wrapi(j - 1, ny)};
+                for (int q = 0; q < 3; ++q) {
+                    const int ii = ci[q], jj = cj[q];
+                    if (k == 0) {
+                        gz[q] = (pp[C3(ii, jj, 1)] - pp[C3(ii, jj, 0)]) / vm->dzf[1];
+                    } else if (k == nz - 1) {
+                        gz[q] = (pp[C3(ii, jj, k)] - pp[C3(ii, jj, k - 1)]) / vm->dzf[k];
+                    } else {
+                        gz[q] = 0.5 * ((pp[C3(ii, jj, k)] - pp[C3(ii, jj, k - 1)]) / vm->dzf[k] +
+                                       (pp[C3(ii, jj, k + 1)] - pp[C3(ii, jj, k)]) / vm->dzf[k + 1]);
+                    }
+                }
+                corr_x = (geo->dc[k] * geo->su[C2(i, j)] / geo->Ju[C2(i, j)]) * (0.5 * (gz[1] + gz[0]));
+                corr_y = (geo->dc[k] * geo->sv[C2(i, j)] / geo->Jv[C2(i, j)]) * (0.5 * (gz[2] + gz[0]));
+            }
+            Uo[c] = U[c] + dtau * (SU[c] - ((pp[c] - pp[C3(wrapi(i - 1, nx), j, k)]) / dx - corr_x));
+            Vo[c] = V[c] + dtau * (SV[c] - ((pp[c] - pp[C3(i, wrapi(j - 1, ny), k)]) / dy - corr_y));
         }
     }
     /* horizontal divergences of the new momentum; rho~ and Theta~ are kept
@@ -593,20 +750,23 @@ static int short_step(const or_grid *g, const or_vmet *vm, const double *const s
             size_t c = C3(i, j, k);
             size_t ce = C3(wrapi(i + 1, nx), j, k), cw = C3(wrapi(i - 1, nx), j, k);
             size_t cn = C3(i, wrapi(j + 1, ny), k), cs = C3(i, wrapi(j - 1, ny), k);
-            double div = (Uo[ce] - Uo[c]) / dx + (Vo[cn] - Vo[c]) / dy;
+            const double jw = geo->Ju[C2(i, j)], je = geo->Ju[C2(wrapi(i + 1, nx), j)];
+            const double js = geo->Jv[C2(i, j)], jn = geo->Jv[C2(i, wrapi(j + 1, ny))];
+            const double jc = geo->J[C2(i, j)];
+            double div = ((je * Uo[ce] - jw * Uo[c]) / dx + (jn * Vo[cn] - js * Vo[c]) / dy) / jc;
             double thw = 0.5 * (ths[cw] + ths[c]), the = 0.5 * (ths[c] + ths[ce]);
             double ths_ = 0.5 * (ths[cs] + ths[c]), thn = 0.5 * (ths[c] + ths[cn]);
-            double tdiv = (the * Uo[ce] - thw * Uo[c]) / dx + (thn * Vo[cn] - ths_ * Vo[c]) / dy;
+            double tdiv = ((the * (je * Uo[ce]) - thw * (jw * Uo[c])) / dx +
+                           (thn * (jn * Vo[cn]) - ths_ * (js * Vo[c])) / dy) / jc;
             rpo[c] = rp[c] - dtau * div;
             tpo[c] = tp[c] + dtau * (RT[c] - tdiv);
         }
     }
     /* vertically implicit part, one tridiagonal system per column */
-    or_col col = {nz, vm->dz, vm->dzf, vm->a, vm->b, g->beta, dtau, g->grav};
 #pragma omp parallel reduction(| : bad)
     {
         size_t nzp = (size_t)nz + 1;
-        double *buf = (double *)malloc(sizeof(double) * nzp * 24);
+        double *buf = (double *)malloc(sizeof(double) * nzp * 27);
         if (!buf) {
             bad |= 2;
         } else {
@@ -617,18 +777,34 @@ static int short_step(const or_grid *g, const or_vmet *vm, const double *const s
             double *thf = buf + 13 * nzp, *pE = buf + 14 * nzp, *rEs = buf + 15 * nzp;
             double *Wp = buf + 16 * nzp, *x = buf + 17 * nzp, *work = buf + 18 * nzp;
             double *orp = buf + 20 * nzp, *otp = buf + 21 * nzp;
+            double *cdz = buf + 22 * nzp, *cdzf = buf + 23 * nzp, *cE = buf + 24 * nzp;
 #pragma omp for schedule(static)
             for (long col_id = 0; col_id < (long)nxy; ++col_id) {
                 int i = (int)(col_id % nx), j = (int)(col_id / nx);
+                const double jc = geo->J[C2(i, j)];
+                const double su0 = geo->su[C2(i, j)], su1 = geo->su[C2(wrapi(i + 1, nx), j)];
+                const double sv0 = geo->sv[C2(i, j)], sv1 = geo->sv[C2(i, wrapi(j + 1, ny))];
                 for (int m = 0; m < nz; ++m) {
                     size_t c = C3(i, j, m);
                     crt[m] = rpo[c]; ctt[m] = tpo[c]; crp[m] = rp[c]; cpp[m] = pp[c];
                     cP0[m] = P0[c]; cCs[m] = Cs[c]; cth[m] = ths[c];
+                    cdz[m] = jc * vm->dz[m];
                 }
                 for (int k = 0; k <= nz; ++k) {
                     cW[k] = W[C3(i, j, k)];
                     cSW[k] = SW[C3(i, j, k)];
+                    cdzf[k] = jc * vm->dzf[k];
+                    cE[k] = 0.0;
+                    if (g->terrain && k > 0 && k < nz) {
+                        /* slope part of Omega from the new horizontal momentum */
+                        const double mxk = 0.5 * (su0 * Uo[C3(i, j, k)] + su1 * Uo[C3(wrapi(i + 1, nx), j, k)]);
+                        const double mxm = 0.5 * (su0 * Uo[C3(i, j, k - 1)] + su1 * Uo[C3(wrapi(i + 1, nx), j, k - 1)]);
+                        const double myk = 0.5 * (sv0 * Vo[C3(i, j, k)] + sv1 * Vo[C3(i, wrapi(j + 1, ny), k)]);
+                        const double mym = 0.5 * (sv0 * Vo[C3(i, j, k - 1)] + sv1 * Vo[C3(i, wrapi(j + 1, ny), k - 1)]);
+                        cE[k] = geo->df[k] * ((vm->a[k] * mxk + vm->b[k] * mxm) + (vm->a[k] * myk + vm->b[k] * mym));
+                    }
                 }
+                or_col col = {nz, cdz, cdzf, vm->a, vm->b, cE, g->beta, dtau, g->grav};
                 col_assemble(&col, crt, ctt, crp, cpp, cP0, cCs, cth, cW, cSW, A, B, Cc, D, thf, pE, rEs);
                 Wp[0] = 0.0;
                 Wp[nz] = 0.0;
@@ -647,6 +823,7 @@ static int short_step(const or_grid *g, const or_vmet *vm, const double *const s
             free(buf);
         }
     }
+#undef C2
     if (bad & 2) return OR_ENOMEM;
     if (bad & 1) return OR_ENOTDOM;
     return OR_OK;
@@ -678,9 +855,14 @@ int or_step(const or_grid *g, double *const st[5], double dt, int n_long, int n_
     const size_t nxy = (size_t)g->nx * g->ny, n = nxy * g->nz, nw = nxy * (g->nz + 1);
     const size_t sz[5] = {n, n, n, nw, n};
     or_vmet vm;
-    if (vmet_init(g, &vm) != OR_OK) { vmet_free(&vm); return OR_ENOMEM; }
+    or_geo geo;
+    memset(&geo, 0, sizeof geo);
+    if (vmet_init(g, &vm) != OR_OK || geo_init(g, &geo) != OR_OK) {
+        vmet_free(&vm); geo_free(&geo);
+        return OR_ENOMEM;
+    }
     double *mem = (double *)malloc(sizeof(double) * (3 * (4 * n + nw) + 6 * n + nw + n));
-    if (!mem) { vmet_free(&vm); return OR_ENOMEM; }
+    if (!mem) { vmet_free(&vm); geo_free(&geo); return OR_ENOMEM; }
     double *bufs[3][5], *sl[7], *pp;
     double *p = mem;
     for (int b = 0; b < 3; ++b)
@@ -705,8 +887,8 @@ int or_step(const or_grid *g, double *const st[5], double dt, int n_long, int n_
             double *const *src = start;
             for (int q = 0; q < n_short; ++q) {
                 double *const *dst = bufs[1 + (q & 1)];
-                int r = short_step(g, &vm, (const double *const *)sl, (const double *const *)src,
-                                   dtau, dst, pp);
+                int r = short_step(g, &vm, &geo, (const double *const *)sl,
+                                   (const double *const *)src, dtau, dst, pp);
                 if (r == OR_ENOMEM) { rc = r; break; }
                 if (r == OR_ENOTDOM) rc = r;
                 if (f32_storage)
@@ -719,6 +901,7 @@ int or_step(const or_grid *g, double *const st[5], double dt, int n_long, int n_
     }
     free(mem);
     vmet_free(&vm);
+    geo_free(&geo);
     return rc;
 }
 
@@ -728,19 +911,30 @@ int or_short_step(const or_grid *g, const double *const sl[7], const double *con
 {
     const size_t n = (size_t)g->nx * g->ny * g->nz;
     or_vmet vm;
-    if (vmet_init(g, &vm) != OR_OK) { vmet_free(&vm); return OR_ENOMEM; }
+    or_geo geo;
+    memset(&geo, 0, sizeof geo);
+    if (vmet_init(g, &vm) != OR_OK || geo_init(g, &geo) != OR_OK) {
+        vmet_free(&vm); geo_free(&geo);
+        return OR_ENOMEM;
+    }
     double *pp = (double *)malloc(n * sizeof(double));
-    if (!pp) { vmet_free(&vm); return OR_ENOMEM; }
-    int rc = short_step(g, &vm, sl, in, dtau, out, pp);
+    if (!pp) { vmet_free(&vm); geo_free(&geo); return OR_ENOMEM; }
+    int rc = short_step(g, &vm, &geo, sl, in, dtau, out, pp);
     free(pp);
     vmet_free(&vm);
+    geo_free(&geo);
     return rc;
 }
 
 /* ------------------------------------------------------------------------
- * Total mass M = sum (rho_ref_k + rho') dx dy dz_k, summed serially in
- * memory order with Neumaier's compensated summation.
+ * Total mass M = sum (rho_ref + rho') J dx dy dz_k, summed serially in
+ * memory order with Neumaier's compensated summation (J = 1 on flat ground).
  * ---------------------------------------------------------------------- */
+static inline double jac_of(const or_grid *g, int i, int j)
+{
+    return g->terrain ? 1.0 - g->terrain[(size_t)j * g->nx + i] / g->zf[g->nz] : 1.0;
+}
+
 double or_mass(const or_grid *g, const double *rp)
 {
     const int nx = g->nx, ny = g->ny, nz = g->nz;
@@ -750,7 +944,8 @@ double or_mass(const or_grid *g, const double *rp)
         double vol = g->dx * g->dy * (g->zf[k + 1] - g->zf[k]);
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
-                double x = (g->rho_ref[k] + rp[C3(i, j, k)]) * vol;
+                size_t c = C3(i, j, k);
+                double x = ((g->rho_ref[RI(g, c, k)] + rp[c]) * vol) * jac_of(g, i, j);
                 double t = s + x;
                 if (fabs(s) >= fabs(x)) comp += (s - t) + x;
                 else comp += (x - t) + s;
@@ -760,14 +955,16 @@ double or_mass(const or_grid *g, const double *rp)
     return s + comp;
 }
 
-/* Diagnostic total energy: sum over cells of volume times
- *   (1/2) [mean(U^2) + mean(V^2) + mean(W^2)] / rho + p/(gamma-1) + rho g z_c
- * with the means taken over the two faces of the cell.  Parity unpinned. */
+/* Diagnostic total energy: sum over cells of volume J dx dy dz times
+ *   (1/2) [mean(U^2) + mean(V^2) + mean(W^2)] / rho + p/(gamma-1) + rho g z
+ * with the means taken over the two faces of the cell and z the true height
+ * of the cell centre.  Parity unpinned. */
 double or_energy(const or_grid *g, const double *const st[5])
 {
     const int nx = g->nx, ny = g->ny, nz = g->nz;
     const size_t nxy = (size_t)nx * ny;
     const double *rp = st[0], *U = st[1], *V = st[2], *W = st[3], *tp = st[4];
+    const double H = g->zf[nz];
     double s = 0.0, comp = 0.0;
     for (int k = 0; k < nz; ++k) {
         double dz = g->zf[k + 1] - g->zf[k];
@@ -776,12 +973,16 @@ double or_energy(const or_grid *g, const double *const st[5])
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
                 size_t c = C3(i, j, k);
-                double rho = g->rho_ref[k] + rp[c];
+                const size_t r = RI(g, c, k);
+                const double h = g->terrain ? g->terrain[(size_t)j * nx + i] : 0.0;
+                const double z = zc + h * (1.0 - zc / H);
+                double rho = g->rho_ref[r] + rp[c];
                 double u2 = 0.5 * (U[c] * U[c] + U[C3(wrapi(i + 1, nx), j, k)] * U[C3(wrapi(i + 1, nx), j, k)]);
                 double v2 = 0.5 * (V[c] * V[c] + V[C3(i, wrapi(j + 1, ny), k)] * V[C3(i, wrapi(j + 1, ny), k)]);
                 double w2 = 0.5 * (W[c] * W[c] + W[C3(i, j, k + 1)] * W[C3(i, j, k + 1)]);
-                double pres = g->p_ref[k] + g->p_ref[k] * expm1(OR_GAMMA * log1p(tp[c] / g->rt_ref[k]));
-                double e = (0.5 * (u2 + v2 + w2) / rho + pres / (OR_GAMMA - 1.0) + rho * g->grav * zc) * vol;
+                double pres = g->p_ref[r] + g->p_ref[r] * expm1(OR_GAMMA * log1p(tp[c] / g->rt_ref[r]));
+                double e = ((0.5 * (u2 + v2 + w2) / rho + pres / (OR_GAMMA - 1.0) + rho * g->grav * z) * vol) *
+                           jac_of(g, i, j);
                 double t = s + e;
                 if (fabs(s) >= fabs(e)) comp += (s - t) + e;
                 else comp += (e - t) + s;

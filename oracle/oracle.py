@@ -45,7 +45,8 @@ class _Grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("donor_cell", ctypes.c_int32), ("dx", ctypes.c_double), ("dy", ctypes.c_double),
                 ("beta", ctypes.c_double), ("grav", ctypes.c_double),
-                ("zf", _dp), ("rho_ref", _dp), ("rt_ref", _dp), ("p_ref", _dp)]
+                ("zf", _dp), ("rho_ref", _dp), ("rt_ref", _dp), ("p_ref", _dp),
+                ("terrain", _dp)]
 
 
 def lib():
@@ -66,7 +67,8 @@ def lib():
         L.or_step.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int,
                               ctypes.c_int, ctypes.c_int]
         L.or_thomas.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
-        col = [ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double] + [_dp] * 9
+        col = [ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+               ctypes.c_double, _dp] + [_dp] * 9
         L.or_vi_assemble.argtypes = col + [_dp] * 4
         L.or_vi_residual.argtypes = col + [_dp, _dp]
         L.or_mass.restype = ctypes.c_double
@@ -96,10 +98,20 @@ class _GridHolder:
         self.rho_ref = _f64(s.rho_ref)
         self.rt_ref = _f64(s.rt_ref)
         self.p_ref = _f64(s.p_ref)
+        h = getattr(s, "terrain", None)
+        self.terrain = None if h is None else _f64(h)
+        if self.terrain is not None:
+            assert self.terrain.shape == (s.ny, s.nx)
+            for r in (self.rho_ref, self.rt_ref, self.p_ref):
+                assert r.shape == (s.nz, s.ny, s.nx)
+        else:
+            for r in (self.rho_ref, self.rt_ref, self.p_ref):
+                assert r.shape == (s.nz,)
         self.g = _Grid(int(s.nx), int(s.ny), int(s.nz), 1 if donor_cell else 0,
                        float(s.dx), float(s.dy),
                        float(s.beta if beta is None else beta), float(grav),
-                       _ptr(self.zf), _ptr(self.rho_ref), _ptr(self.rt_ref), _ptr(self.p_ref))
+                       _ptr(self.zf), _ptr(self.rho_ref), _ptr(self.rt_ref), _ptr(self.p_ref),
+                       _dp() if self.terrain is None else _ptr(self.terrain))
 
     @property
     def ref(self):
@@ -192,31 +204,42 @@ def thomas(a, b, c, d):
     return x, rc
 
 
-def _col_args(zf, beta, dtau, grav, col):
+def _col_args(zf, beta, dtau, grav, col, jac=1.0, E=None):
     keys = ("rt", "tt", "rp", "pp", "P0", "Cs", "ths", "W", "SW")
     arrs = [_f64(col[k]) for k in keys]
-    return arrs, [len(zf) - 1, _ptr(_f64(zf)), float(beta), float(dtau), float(grav)] + \
-        [_ptr(a) for a in arrs]
+    zf = _f64(zf)
+    arrs.append(zf)
+    e = _dp()
+    if E is not None:
+        E = _f64(E)
+        assert E.shape == (len(zf),)
+        arrs.append(E)
+        e = _ptr(E)
+    return arrs, [len(zf) - 1, _ptr(zf), float(beta), float(dtau), float(grav), float(jac), e] + \
+        [_ptr(a) for a in arrs[:9]]
 
 
-def vi_assemble(zf, beta, dtau, grav, col):
-    """(A, B, C, D) indexed by level face (nz+1 entries, 1..nz-1 meaningful)."""
+def vi_assemble(zf, beta, dtau, grav, col, jac=1.0, E=None):
+    """(A, B, C, D) indexed by level face (nz+1 entries, 1..nz-1 meaningful).
+
+    jac: the column's Jacobian J (thicknesses J dzeta); E: the slope part of
+    the flux through the zeta surfaces per level face (None: zero)."""
     zf = _f64(zf)
     nz = len(zf) - 1
     out = [np.zeros(nz + 1) for _ in range(4)]
-    keep, args = _col_args(zf, beta, dtau, grav, col)
+    keep, args = _col_args(zf, beta, dtau, grav, col, jac, E)
     rc = lib().or_vi_assemble(*args, *[_ptr(o) for o in out])
     if rc != OK:
         raise RuntimeError(rc)
     return out
 
 
-def vi_residual(zf, beta, dtau, grav, col, Wp):
+def vi_residual(zf, beta, dtau, grav, col, Wp, jac=1.0, E=None):
     zf = _f64(zf)
     nz = len(zf) - 1
     R = np.zeros(nz + 1)
     Wp = _f64(Wp)
-    keep, args = _col_args(zf, beta, dtau, grav, col)
+    keep, args = _col_args(zf, beta, dtau, grav, col, jac, E)
     rc = lib().or_vi_residual(*args, _ptr(Wp), _ptr(R))
     if rc != OK:
         raise RuntimeError(rc)

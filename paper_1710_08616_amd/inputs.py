@@ -15,6 +15,10 @@ sub-block of a field can be regenerated without drawing the rest.
 
 Layout: canonical i-fastest.  Cell fields have shape (nz, ny, nx); the
 vertical momentum lives on the nz+1 level faces, shape (nz+1, ny, nx).
+
+Terrain: a state may carry surface heights h (shape (ny, nx)); the cell
+centres then sit at the true heights z = zeta + h (1 - zeta/H), and the
+reference arrays are given per cell (shape (nz, ny, nx)) at those heights.
 """
 from __future__ import annotations
 
@@ -153,6 +157,7 @@ class State:
     n_long: int = 10
     beta: float = 0.55
     name: str = ""
+    terrain: Optional[np.ndarray] = None   # (ny, nx) surface heights; refs are 3D
 
     @property
     def cells(self) -> int:
@@ -165,6 +170,35 @@ class State:
         """The same state with every field rounded to binary32 (kept as float64)."""
         return dataclasses.replace(
             self, fields=[f.astype(np.float32).astype(np.float64) for f in self.fields])
+
+
+def true_heights(zc: np.ndarray, terrain: Optional[np.ndarray]) -> np.ndarray:
+    """Heights of the cell centres: zc as an (nz, 1, 1) column on flat
+    ground, zc + h (1 - zc/H) of shape (nz, ny, nx) over terrain h."""
+    zc = np.asarray(zc, dtype=np.float64)[:, None, None]
+    if terrain is None:
+        return zc
+    return zc + terrain[None] * (1.0 - zc / H_TOP)
+
+
+def orography(nx: int, ny: int, dx: float, dy: float, seed: int, hmax: float = 2000.0,
+              hills: int = 8, smin: float = 8000.0, smax: float = 40000.0) -> np.ndarray:
+    """Sum of ``hills`` Gaussian hills a exp(-r^2 / (2 sigma^2)), r the periodic
+    horizontal distance to a centre ~ U over the domain, sigma ~ U[smin, smax],
+    a ~ U[0.3, 1]; rescaled so that the highest point is ``hmax``."""
+    rng = np.random.default_rng(seed)
+    lx, ly = nx * dx, ny * dy
+    x = (np.arange(nx) + 0.5) * dx
+    y = (np.arange(ny) + 0.5) * dy
+    h = np.zeros((ny, nx))
+    for _ in range(hills):
+        sig = rng.uniform(smin, smax)
+        amp = rng.uniform(0.3, 1.0)
+        xc, yc = rng.uniform(0.0, lx), rng.uniform(0.0, ly)
+        ddx = _periodic_dist(x, xc, lx)[None, :]
+        ddy = _periodic_dist(y, yc, ly)[:, None]
+        h += amp * np.exp(-(ddx * ddx + ddy * ddy) / (2.0 * sig * sig))
+    return h * (hmax / h.max())
 
 
 def _periodic_dist(x: np.ndarray, xc: float, length: float) -> np.ndarray:
@@ -216,32 +250,45 @@ def make_state(nx: int, ny: int, nz: int, dx: float = 2000.0, dy: float = 2000.0
                seed: int = 1710, bubbles: Optional[list] = None, u_bg: float = 10.0,
                v_bg: float = 0.0, noise: float = 0.1, dt: float = 10.0, n_short: int = 4,
                n_long: int = 10, beta: float = 0.55, zf: Optional[np.ndarray] = None,
-               reference: str = "isothermal", name: str = "") -> State:
+               reference: str = "isothermal", name: str = "",
+               terrain: Optional[np.ndarray] = None, shear: float = 0.0) -> State:
     """Warm-bubble state at constant pressure in a uniform wind plus noise.
 
     Theta' = 0 and rho' = rhotheta_ref / (theta_ref + theta_bubble) - rho_ref,
-    so the pressure is the reference pressure everywhere.  U = rho_u (u_bg + n)
-    with rho_u the two-point mean density on the x-face and n ~ N(0, noise^2);
-    V likewise; W = rho_w n on interior faces and 0 on the lids.
+    so the pressure is the reference pressure everywhere.  U = rho_u (u + n)
+    with rho_u the two-point mean density on the x-face, u = u_bg +
+    shear * z / H (z the mean true height of the face's two cells) and
+    n ~ N(0, noise^2); V likewise with v_bg; W = rho_w n on interior faces and
+    0 on the lids.  With ``terrain`` (surface heights, (ny, nx)) the reference
+    is evaluated at every cell's true height; the bubbles stay defined in the
+    zeta coordinate.
     """
     zf = levels(nz) if zf is None else np.asarray(zf, dtype=np.float64)
     zc = centres(zf)
+    if terrain is not None:
+        terrain = np.ascontiguousarray(terrain, dtype=np.float64)
+        assert terrain.shape == (ny, nx)
+    z3 = true_heights(zc, terrain)
     if reference == "isothermal":
-        rho_ref, rt_ref, p_ref = reference_isothermal(zc)
+        rho_ref, rt_ref, p_ref = reference_isothermal(z3)
     elif reference == "neutral":
-        rho_ref, rt_ref, p_ref = reference_neutral(zc)
+        rho_ref, rt_ref, p_ref = reference_neutral(z3)
     else:
         raise ValueError(reference)
     th_ref = rt_ref / rho_ref
     if bubbles is None:
         bubbles = [(0.5 * nx * dx, 0.5 * ny * dy, 5000.0, 4000.0)]
     thb = bubble_theta(nx, ny, zc, dx, dy, bubbles)
-    rho_full = rt_ref[:, None, None] / (th_ref[:, None, None] + thb)
-    rho_p = rho_full - rho_ref[:, None, None]
+    rho_full = rt_ref / (th_ref + thb)
+    rho_p = rho_full - rho_ref
     rt_p = np.zeros((nz, ny, nx))
     rho_u = 0.5 * (np.roll(rho_full, 1, axis=2) + rho_full)
     rho_v = 0.5 * (np.roll(rho_full, 1, axis=1) + rho_full)
-    U = rho_u * (u_bg + noise * gaussian(seed, 0, (nz, ny, nx)))
+    u_prof = u_bg
+    if shear != 0.0:
+        zb = np.broadcast_to(z3, (nz, ny, nx))
+        u_prof = u_bg + shear * (0.5 * (np.roll(zb, 1, axis=2) + zb)) / H_TOP
+    U = rho_u * (u_prof + noise * gaussian(seed, 0, (nz, ny, nx)))
     V = rho_v * (v_bg + noise * gaussian(seed, 1, (nz, ny, nx)))
     dz = np.diff(zf)
     W = np.zeros((nz + 1, ny, nx))
@@ -250,9 +297,11 @@ def make_state(nx: int, ny: int, nz: int, dx: float = 2000.0, dy: float = 2000.0
         b = dz[1:] / (dz[:-1] + dz[1:])            # weight of the cell below face k
         rho_w = a[:, None, None] * rho_full[1:] + b[:, None, None] * rho_full[:-1]
         W[1:nz] = rho_w * noise * gaussian(seed, 2, (nz + 1, ny, nx))[1:nz]
+    if terrain is None:
+        rho_ref, rt_ref, p_ref = (np.ascontiguousarray(r[:, 0, 0]) for r in (rho_ref, rt_ref, p_ref))
     return State(nx, ny, nz, dx, dy, zf, rho_ref, rt_ref, p_ref,
                  [rho_p, U, V, W, rt_p], dt=dt, n_short=n_short, n_long=n_long,
-                 beta=beta, name=name)
+                 beta=beta, name=name, terrain=terrain)
 
 
 def rest_state(nx, ny, nz, dx=2000.0, dy=2000.0, zf=None, reference="isothermal",
@@ -311,6 +360,10 @@ def workload(name: str) -> State:
     large_sub   128x128x64 sub-run of the same generator (oracle-sized).
     xl          2048x2048x64, the same generator with 16 bubbles, 30 long steps,
                 n = 6 (the layout-comparison domain; flat lower boundary).
+    terrain     1600x1280x64 over 8 Gaussian hills (max 2 km), 16 bubbles, wind
+                shear u = 30 z/H, 50 long steps, n = 6.
+    terrain_sub 160x128x64 sub-run of the same generator (oracle-sized; hills
+                and bubbles drawn for that domain).
     """
     if name == "small":
         return make_state(64, 64, 32, seed=1710, dt=10.0, n_short=4, n_long=10, name=name)
@@ -319,6 +372,13 @@ def workload(name: str) -> State:
         bub = random_bubbles(seed, 16, 2048 * 2000.0, 2048 * 2000.0)
         return make_state(2048, 2048, 64, seed=seed, bubbles=bub, dt=10.0, n_short=6,
                           n_long=30, name=name)
+    if name in ("terrain", "terrain_sub"):
+        nx, ny = (1600, 1280) if name == "terrain" else (160, 128)
+        seed = 1712
+        h = orography(nx, ny, 2000.0, 2000.0, seed)
+        bub = random_bubbles(seed, 16, nx * 2000.0, ny * 2000.0)
+        return make_state(nx, ny, 64, seed=seed, bubbles=bub, u_bg=0.0, shear=30.0,
+                          terrain=h, dt=10.0, n_short=6, n_long=50, name=name)
     if name in ("large", "large_sub"):
         n = 1024 if name == "large" else 128
         seed = 1711

@@ -61,20 +61,27 @@ def _column(nz, seed, zf, scale=1.0):
     return col
 
 
-@pytest.mark.parametrize("nz,stretched,beta,dtau", [(8, True, 0.55, 2.5), (8, False, 0.5, 1.0),
-                                                    (32, True, 0.55, 2.5), (64, True, 0.7, 1.6)])
-def test_assembly_is_jacobian_of_update_equations(oracle, nz, stretched, beta, dtau):
+@pytest.mark.parametrize("nz,stretched,beta,dtau,terrain",
+                         [(8, True, 0.55, 2.5, False), (8, False, 0.5, 1.0, False),
+                          (32, True, 0.55, 2.5, False), (64, True, 0.7, 1.6, False),
+                          (8, True, 0.55, 2.5, True), (32, True, 0.6, 2.0, True)])
+def test_assembly_is_jacobian_of_update_equations(oracle, nz, stretched, beta, dtau, terrain):
+    """Over terrain the column has J < 1 and a nonzero slope flux E."""
     zf = inputs.levels(nz) if stretched else inputs.uniform_levels(nz, 8000.0)
     col = _column(nz, nz * 7 + 1, zf)
-    A, B, C, D = oracle.vi_assemble(zf, beta, dtau, GRAV, col)
-    r0 = oracle.vi_residual(zf, beta, dtau, GRAV, col, np.zeros(nz + 1))
+    jac, E = 1.0, None
+    if terrain:
+        jac = 0.9
+        E = np.concatenate([[0.0], 0.3 * np.random.default_rng(nz).normal(size=nz - 1), [0.0]])
+    A, B, C, D = oracle.vi_assemble(zf, beta, dtau, GRAV, col, jac, E)
+    r0 = oracle.vi_residual(zf, beta, dtau, GRAV, col, np.zeros(nz + 1), jac, E)
     # the residual is affine in W+: R(W+) = M W+ - D
     assert np.allclose(-r0[1:nz], D[1:nz], rtol=1e-12, atol=1e-12 * np.abs(D).max())
     M = np.zeros((nz - 1, nz - 1))
     for jcol in range(1, nz):
         e = np.zeros(nz + 1)
         e[jcol] = 1.0
-        M[:, jcol - 1] = (oracle.vi_residual(zf, beta, dtau, GRAV, col, e) - r0)[1:nz]
+        M[:, jcol - 1] = (oracle.vi_residual(zf, beta, dtau, GRAV, col, e, jac, E) - r0)[1:nz]
     T = np.diag(B[1:nz]) + np.diag(A[2:nz], -1) + np.diag(C[1:nz - 1], 1)
     assert np.max(np.abs(M - T)) <= 1e-11 * np.max(np.abs(T))
     # nothing outside the three diagonals

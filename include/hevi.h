@@ -18,6 +18,16 @@
  *    momentum rho*w has nx*ny*(nz+1) values (level faces 0..nz), and its
  *    two lid levels must be 0.  U = rho*u sits on the west face of cell i,
  *    V = rho*v on the south face of cell j; the domain is periodic in x and y.
+ *  - Terrain (optional): surface heights h(x, y) give the terrain-following
+ *    height z = zeta + h (1 - zeta/H) of Gal-Chen & Somerville (1975), with
+ *    H = zeta_faces[nz].  Cell volumes are J dx dy dzeta with J = 1 - h/H per
+ *    column; horizontal mass fluxes carry the face J (mean of the two
+ *    columns); the flux through the zeta surfaces is
+ *    Omega = W - (1 - zeta/H) (dh/dx U + dh/dy V, face slopes as differences
+ *    of h, averaged to the level face) and is zero on both lids, where W is
+ *    held at 0; the horizontal pressure gradient along a zeta surface is
+ *    corrected by (dz/dx / J) dp'/dzeta.  The paper's Sect. 1.1 fixes the
+ *    finite-volume form; the coordinate is a stated reading.
  *  - Host pointers are borrowed for the duration of the call only.
  *  - Device memory: the caller owns one workspace of at least
  *    hv_workspace_bytes() bytes (any device allocation, 256-byte aligned);
@@ -72,7 +82,9 @@ typedef struct {
     int32_t nx, ny, nz;        /* cells; nx, ny >= 4; nz in {32, 64, 128}    */
     double dx, dy;             /* horizontal spacing (m), > 0                */
     const double *zeta_faces;  /* nz+1 increasing level heights, [0] = 0     */
-    const double *terrain;     /* must be NULL: flat lower boundary          */
+    const double *terrain;     /* NULL (flat) or nx*ny surface heights h (m),
+                                  i fastest, with 1 - h/H >= 0.1; borrowed
+                                  during create                             */
     int32_t precision;         /* HV_FP64 / HV_FP32 / HV_MIXED               */
     int32_t layout;            /* HV_KIJ or HV_IJK                           */
     double beta;               /* off-centring of the vertical solve, in [0.5, 1] */
@@ -92,9 +104,11 @@ int hv_grid_create(const hv_grid_desc *desc, void *dev_workspace, size_t bytes,
 
 /* Load a state (the paper's copy-in at the start of a run).  fields[f] for
  * f = HV_RHO_PTB..HV_RHOTHETA_PTB as described above; rho_ref, rhotheta_ref
- * and p_ref are the reference columns at the nz cell centres.  Values are
- * converted to the grid's precision and layout.  Non-finite input, or a
- * non-zero rho*w on a lid, returns HV_ERR_ARG.  Synchronises the stream. */
+ * and p_ref are the reference state at the cell centres: nz values (one
+ * column) on flat ground, nx*ny*nz values in canonical order over terrain.
+ * Values are converted to the grid's precision and layout.  Non-finite
+ * input, non-positive reference values, or a non-zero rho*w on a lid,
+ * returns HV_ERR_ARG.  Synchronises the stream. */
 int hv_state_init(hv_grid_t g, const double *const fields[5], const double *rho_ref,
                   const double *rhotheta_ref, const double *p_ref);
 
@@ -114,7 +128,7 @@ int hv_step(hv_grid_t g, double dt, int32_t n_long, int32_t n_short);
  * nx*ny*(nz+1) for HV_RHOW.  Synchronises the stream. */
 int hv_state_read(hv_grid_t g, int32_t field, double *host_out);
 
-/* Total mass sum (rho_ref + rho') dx dy dz and the diagnostic total energy
+/* Total mass sum (rho_ref + rho') J dx dy dzeta and the diagnostic total energy
  * (kinetic + internal + potential) of the current state, in float64 with a
  * fixed summation order.  Either output pointer may be NULL.  Returns
  * HV_ERR_NONFINITE if the mass of the current state is not finite (a

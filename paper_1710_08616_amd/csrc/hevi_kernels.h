@@ -25,34 +25,51 @@ enum VmField {
     VM_P,          // reference pressure
     VM_VOL,        // cell volume dx*dy*dz_k
     VM_ZC,         // height of the centre of cell k
+    VM_DC,         // 1 - zeta/H at the centre of cell k (terrain decay)
+    VM_DF,         // 1 - zeta/H at level face k
     VM_NFIELDS
 };
 
-// One domain as every kernel sees it (device memory, one record per member).
-// roles[0] is the buffer holding the state at the start of a long step (and
-// the current state between steps); roles[1], roles[2] are the two running
-// buffers.  The rotate kernel updates roles at the end of each long step, so
-// one captured launch sequence serves every long step.
+// Per-column geometry of a terrain-following grid (float64, 8 per column,
+// column-major i-fastest): Jacobians and slopes of z = zeta + h (1 - zeta/H).
+enum GeoField {
+    GEO_J = 0,     // J = 1 - h/H of the column
+    GEO_JU,        // J on the west x-face (mean of the two columns)
+    GEO_JV,        // J on the south y-face
+    GEO_SU,        // dh/dx on the west x-face
+    GEO_SV,        // dh/dy on the south y-face
+    GEO_H,         // surface height h
+    GEO_NFIELDS = 8
+};
+
+// One domain as every kernel sees it: sizes, spacings, long step and the
+// device arrays carved from the workspace.
 struct MemberDev {
     int nx, ny, nz, npart;       // npart: mass partials of this member
-    int roles[4];
     double rdx, rdy, beta, dt;   // dt: long step of this member
     const double *vm;
     double *partials;
     double *sums;                // [0] perturbation mass, [1] energy
     void *st[3][5];              // rho', U, V, W, Theta' of the three buffers
     void *slow[7];               // S_U, S_V, S_W, R_Theta, theta_s, P0_s, C_s
-    void *spec[3];               // u, v, w of the stage input
+    void *spec[4];               // u, v, w of the stage input; [3] Omega (terrain)
+    const double *geo;           // terrain: GEO_NFIELDS per column, else null
+    void *ref[3];                // terrain: rho_ref, rhotheta_ref, p_ref per cell
 };
 
-// One launch covering the blocks of a group of members (all with the same nz).
+// One launch over the blocks of a group of members (all with the same nz).
+// A group of one member names it directly; a larger group maps each block to
+// (member id, tile) through a per-block table.
 struct Group {
     const MemberDev *mem;   // device member table
-    const int *ids;         // device: member ids of the group (nm)
-    const int *prefix;      // device: prefix sums of the members' block counts (nm + 1)
+    const int *ids;         // device: member ids of the group
+    const unsigned *blk;    // device: per block, member id << 24 | tile (nm > 1)
     int nm;                 // members in the group
-    int nblocks;            // blocks of the launch (= prefix[nm])
+    int first;              // member id when nm == 1
+    int nblocks;            // blocks of the launch
     int ti_log2;            // tile = (1 << ti_log2) columns along x by 16 >> ti_log2 along y
+    int src, dst;           // state buffers read and written by this launch
+    int terrain;            // members of the group are terrain-following
 };
 
 // Blocks a member needs for a tile shape.
@@ -69,18 +86,13 @@ inline int partials_of(int nx, int ny)
 
 // prec: 0 float64, 1 float32, 2 float32 sweeps + float64 column solve.
 // layout: 0 i-fastest, 1 column-fastest.  L = nz / 16.
-hipError_t launch_slow_prep(int prec, int layout, int L, const Group &gr, int stage, int n_short,
-                            hipStream_t s);
-hipError_t launch_slow_flux(int prec, int layout, int L, const Group &gr, int stage, int n_short,
-                            hipStream_t s);
-hipError_t launch_short_step(int prec, int layout, int L, const Group &gr, int stage, int sub,
-                             int n_short, hipStream_t s);
-// gr: prefix over the members' partial counts.  Sums the perturbation mass
-// (energy = false) or the total energy of the current state into sums.
+// Slow sweep of stage `stage` on buffer gr.src.
+hipError_t launch_slow_prep(int prec, int layout, int L, const Group &gr, hipStream_t s);
+hipError_t launch_slow_flux(int prec, int layout, int L, const Group &gr, hipStream_t s);
+// Short step gr.src -> gr.dst of length (member dt) * frac.
+hipError_t launch_short_step(int prec, int layout, int L, const Group &gr, double frac, hipStream_t s);
+// gr.blk maps blocks to (member, partial).  Sums the perturbation mass
+// (energy = false) or the total energy of buffer gr.src into each member's sums.
 hipError_t launch_sums(int prec, int layout, int L, const Group &gr, bool energy, hipStream_t s);
-// After the last short step: make the long step's result the current state.
-hipError_t launch_rotate(MemberDev *mem, int n, int n_short, hipStream_t s);
-// Set the long-step length of member q.
-hipError_t launch_set_dt(MemberDev *mem, int q, double dt, hipStream_t s);
 
 }  // namespace hv

@@ -51,39 +51,30 @@ using vec_t = T __attribute__((ext_vector_type(L)));
 
 __device__ __forceinline__ int wrapc(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-// Block -> (member, tile) -> this segment's column.  A launch covers the
-// blocks of every member of a group; prefix[] holds the members' first
-// blocks.  A tile is (1 << ti_log2) columns along x by 16 >> ti_log2 along y.
+// Block -> (member, tile) -> this segment's column.  A tile is (1 << ti_log2)
+// columns along x by 16 >> ti_log2 along y.
 struct Where {
     const MemberDev *m;
-    int i, j, t;
+    int i, j;
     bool active;
 };
 __device__ __forceinline__ Where locate(const Group &gr)
 {
-    const int b = (int)blockIdx.x;
-    int lo = 0, hi = gr.nm;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (gr.prefix[mid] <= b) lo = mid;
-        else hi = mid;
-    }
     Where w;
-    w.m = gr.mem + gr.ids[lo];
-    w.t = b - gr.prefix[lo];
+    int t = (int)blockIdx.x, id = gr.first;
+    if (gr.nm > 1) {
+        const unsigned v = gr.blk[blockIdx.x];
+        t = (int)(v & 0xFFFFFFu);
+        id = (int)(v >> 24);
+    }
+    w.m = gr.mem + id;
     const int ti = 1 << gr.ti_log2, tj = kColsPerBlock >> gr.ti_log2;
     const int tiles_x = (w.m->nx + ti - 1) / ti;
     const int c = (int)threadIdx.x / SEG;
-    w.i = (w.t % tiles_x) * ti + (c & (ti - 1));
-    w.j = (w.t / tiles_x) * tj + (c >> gr.ti_log2);
+    w.i = (t % tiles_x) * ti + (c & (ti - 1));
+    w.j = (t / tiles_x) * tj + (c >> gr.ti_log2);
     w.active = w.i < w.m->nx && w.j < w.m->ny;
     return w;
-}
-
-// buffer roles: the stage input of stage s, and the source/target of short step q
-__device__ __forceinline__ int stage_input(const MemberDev *m, int s, int n)
-{
-    return s == 0 ? m->roles[0] : m->roles[1 + ((n - 1) & 1)];
 }
 
 // Storage orders of a 3D field with nz levels per column.
@@ -101,6 +92,9 @@ struct IJK {
         return ((size_t)k * ny + j) * nx + i;
     }
 };
+
+// Field f of state buffer b.
+__device__ __forceinline__ void *buf(const MemberDev *m, int b, int f) { return m->st[b][f]; }
 
 template <class Lay, int L>
 struct Lane {
@@ -156,6 +150,11 @@ struct Lane {
 #pragma unroll
             for (int l = 0; l < L; ++l) __builtin_nontemporal_store((T)x[l], q + (size_t)l * kstride);
         }
+    }
+    // per-column geometry value f of column (i+di, j+dj)
+    __device__ double geo(const double *__restrict__ g, int f, int di, int dj) const
+    {
+        return g[((size_t)wrapc(j + dj, ny) * nx + wrapc(i + di, nx)) * GEO_NFIELDS + f];
     }
     // per-level constant of the lane's levels (+ offset), as type S
     template <typename S>
@@ -225,46 +224,50 @@ __device__ __forceinline__ T kface(T qLL, T qL, T qR, T qRR, T m)
 // --------------------------------------------------------------------------
 // slow sweep, part 1: specific velocities, theta and stage coefficients
 // --------------------------------------------------------------------------
-template <typename T, class Lay, int L>
-__global__ __launch_bounds__(BLOCK) void k_slow_prep(Group gr, int stage, int n_short)
+template <typename T, class Lay, int L, bool TR>
+__device__ __forceinline__ void prep_body(
+    const Lane<Lay, L> &ln, const double *__restrict__ vm, const double *__restrict__ geo,
+    const T *__restrict__ rref3, const T *__restrict__ rtref3, const T *__restrict__ pref3,
+    const T *__restrict__ rp, const T *__restrict__ U, const T *__restrict__ V,
+    const T *__restrict__ W, const T *__restrict__ tp, T *__restrict__ uo, T *__restrict__ vo,
+    T *__restrict__ wo, T *__restrict__ tho, T *__restrict__ P0o, T *__restrict__ Cso,
+    T *__restrict__ omo)
 {
-    const Where wh = locate(gr);
-    if (!wh.active) return;
-    const MemberDev *m = wh.m;
-    const Lane<Lay, L> ln(m->nx, m->ny, m->nz, wh.i, wh.j);
-    const double *__restrict__ vm = m->vm;
-    void *const *in = m->st[stage_input(m, stage, n_short)];
-    const T *__restrict__ rp = (const T *)in[0];
-    const T *__restrict__ U = (const T *)in[1];
-    const T *__restrict__ V = (const T *)in[2];
-    const T *__restrict__ W = (const T *)in[3];
-    const T *__restrict__ tp = (const T *)in[4];
-    T *__restrict__ uo = (T *)m->spec[0];
-    T *__restrict__ vo = (T *)m->spec[1];
-    T *__restrict__ wo = (T *)m->spec[2];
-    T *__restrict__ tho = (T *)m->slow[4];
-    T *__restrict__ P0o = (T *)m->slow[5];
-    T *__restrict__ Cso = (T *)m->slow[6];
-
     T r0[L], rw[L], rs[L], Uc[L], Vc[L], Wc[L], tc[L];
     ln.load(rp, 0, 0, r0);
     ln.load(rp, -1, 0, rw);
     ln.load(rp, 0, -1, rs);
-    ln.template load<true>(U, 0, 0, Uc);
-    ln.template load<true>(V, 0, 0, Vc);
+    // over terrain the neighbours read U and V too (for Omega)
+    ln.template load<!TR>(U, 0, 0, Uc);
+    ln.template load<!TR>(V, 0, 0, Vc);
     ln.template load<true>(W, 0, 0, Wc);
     ln.template load<true>(tp, 0, 0, tc);
     T rref[L], rtref[L], pref[L], a[L], b[L];
-    ln.vmet(vm, VM_RHO, rref);
-    ln.vmet(vm, VM_RT, rtref);
-    ln.vmet(vm, VM_P, pref);
     ln.vmet(vm, VM_A, a);
     ln.vmet(vm, VM_B, b);
+    if constexpr (TR) {
+        T rrw[L], rrs[L];
+        ln.load(rref3, 0, 0, rref);
+        ln.load(rref3, -1, 0, rrw);
+        ln.load(rref3, 0, -1, rrs);
+        ln.template load<true>(rtref3, 0, 0, rtref);
+        ln.template load<true>(pref3, 0, 0, pref);
 #pragma unroll
-    for (int l = 0; l < L; ++l) {
-        r0[l] = rref[l] + r0[l];
-        rw[l] = rref[l] + rw[l];
-        rs[l] = rref[l] + rs[l];
+        for (int l = 0; l < L; ++l) {
+            r0[l] = rref[l] + r0[l];
+            rw[l] = rrw[l] + rw[l];
+            rs[l] = rrs[l] + rs[l];
+        }
+    } else {
+        ln.vmet(vm, VM_RHO, rref);
+        ln.vmet(vm, VM_RT, rtref);
+        ln.vmet(vm, VM_P, pref);
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            r0[l] = rref[l] + r0[l];
+            rw[l] = rref[l] + rw[l];
+            rs[l] = rref[l] + rs[l];
+        }
     }
     const T rbelow = from_below(r0[L - 1]);
     T u[L], v[L], w[L], th[L], P0[L], Cs[L];
@@ -287,16 +290,63 @@ __global__ __launch_bounds__(BLOCK) void k_slow_prep(Group gr, int stage, int n_
     ln.store(tho, th);
     ln.store(P0o, P0);
     ln.store(Cso, Cs);
+    if constexpr (TR) {
+        // flux through the zeta surfaces: Omega = W - (1 - zeta/H) * (slope-
+        // weighted U and V averaged to the column centre, then linearly to
+        // the level face); zero on the bottom lid
+        T U1[L], V1[L], df[L];
+        ln.load(U, 1, 0, U1);
+        ln.load(V, 0, 1, V1);
+        ln.vmet(vm, VM_DF, df);
+        const T su0 = (T)ln.geo(geo, GEO_SU, 0, 0), su1 = (T)ln.geo(geo, GEO_SU, 1, 0);
+        const T sv0 = (T)ln.geo(geo, GEO_SV, 0, 0), sv1 = (T)ln.geo(geo, GEO_SV, 0, 1);
+        T mx[L], my[L];
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            mx[l] = T(0.5) * (su0 * Uc[l] + su1 * U1[l]);
+            my[l] = T(0.5) * (sv0 * Vc[l] + sv1 * V1[l]);
+        }
+        const T mxb = from_below(mx[L - 1]), myb = from_below(my[L - 1]);
+        T om[L];
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            const int k = ln.k0 + l;
+            const T mxm = (l == 0) ? mxb : mx[l - 1];
+            const T mym = (l == 0) ? myb : my[l - 1];
+            const T e = df[l] * ((a[l] * mx[l] + b[l] * mxm) + (a[l] * my[l] + b[l] * mym));
+            om[l] = (k == 0) ? T(0) : Wc[l] - e;
+        }
+        ln.store(omo, om);
+    }
+}
+
+template <typename T, class Lay, int L, bool TR>
+__global__ __launch_bounds__(BLOCK) void k_slow_prep(Group gr)
+{
+    const Where wh = locate(gr);
+    if (!wh.active) return;
+    const MemberDev *m = wh.m;
+    const Lane<Lay, L> ln(m->nx, m->ny, m->nz, wh.i, wh.j);
+    prep_body<T, Lay, L, TR>(ln, m->vm, m->geo, (const T *)m->ref[0], (const T *)m->ref[1],
+                             (const T *)m->ref[2], (const T *)buf(m, gr.src, 0),
+                             (const T *)buf(m, gr.src, 1), (const T *)buf(m, gr.src, 2),
+                             (const T *)buf(m, gr.src, 3), (const T *)buf(m, gr.src, 4),
+                             (T *)m->spec[0], (T *)m->spec[1], (T *)m->spec[2], (T *)m->slow[4],
+                             (T *)m->slow[5], (T *)m->slow[6], (T *)m->spec[3]);
 }
 
 // --------------------------------------------------------------------------
 // slow sweep, part 2: advective tendencies S_U, S_V, S_W and R_Theta
 // --------------------------------------------------------------------------
-template <typename T, class Lay, int L>
+// Over terrain (TR) every horizontal mass flux carries the face Jacobian,
+// the momentum control volumes take means of the cell-face fluxes, the
+// vertical mass flux is Omega (Wz = Omega, else Wz = W) and each tendency is
+// divided by the Jacobian of its control volume.
+template <typename T, class Lay, int L, bool TR>
 __device__ __forceinline__ void slow_su(const Lane<Lay, L> &ln, T rdx, T rdy, const T (&rdz)[L],
-                                        const T *__restrict__ U, const T *__restrict__ V,
-                                        const T *__restrict__ W, const T *__restrict__ uu,
-                                        T *__restrict__ SU)
+                                        const double *__restrict__ geo, const T *__restrict__ U,
+                                        const T *__restrict__ V, const T *__restrict__ Wz,
+                                        const T *__restrict__ uu, T *__restrict__ SU)
 {
     T ux[5][L], uy[4][L];
 #pragma unroll
@@ -313,8 +363,18 @@ __device__ __forceinline__ void slow_su(const Lane<Lay, L> &ln, T rdx, T rdy, co
     ln.load(V, 0, 0, V00);
     ln.load(V, -1, 1, Vw1);
     ln.load(V, 0, 1, V01);
-    ln.load(W, -1, 0, Wm);
-    ln.load(W, 0, 0, W0);
+    ln.load(Wz, -1, 0, Wm);
+    ln.load(Wz, 0, 0, W0);
+    T jum = T(1), ju0 = T(1), jup = T(1), jvw0 = T(1), jv00 = T(1), jvw1 = T(1), jv01 = T(1);
+    if constexpr (TR) {
+        jum = (T)ln.geo(geo, GEO_JU, -1, 0);
+        ju0 = (T)ln.geo(geo, GEO_JU, 0, 0);
+        jup = (T)ln.geo(geo, GEO_JU, 1, 0);
+        jvw0 = (T)ln.geo(geo, GEO_JV, -1, 0);
+        jv00 = (T)ln.geo(geo, GEO_JV, 0, 0);
+        jvw1 = (T)ln.geo(geo, GEO_JV, -1, 1);
+        jv01 = (T)ln.geo(geo, GEO_JV, 0, 1);
+    }
     T ue[L + 4];
     extend2(ux[2], ue, ln.p, false);
     const bool top = (ln.p == SEG - 1);
@@ -334,24 +394,34 @@ __device__ __forceinline__ void slow_su(const Lane<Lay, L> &ln, T rdx, T rdy, co
     T out[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) {
-        const T m0 = T(0.5) * (Um[l] + U0[l]);
+        T m0, m1, n0, n1;
+        if constexpr (TR) {
+            m0 = T(0.5) * (jum * Um[l] + ju0 * U0[l]);
+            m1 = T(0.5) * (ju0 * U0[l] + jup * Up[l]);
+            n0 = T(0.5) * (jvw0 * Vw0[l] + jv00 * V00[l]);
+            n1 = T(0.5) * (jvw1 * Vw1[l] + jv01 * V01[l]);
+        } else {
+            m0 = T(0.5) * (Um[l] + U0[l]);
+            m1 = T(0.5) * (U0[l] + Up[l]);
+            n0 = T(0.5) * (Vw0[l] + V00[l]);
+            n1 = T(0.5) * (Vw1[l] + V01[l]);
+        }
         const T fx0 = m0 * kface(ux[0][l], ux[1][l], ux[2][l], ux[3][l], m0);
-        const T m1 = T(0.5) * (U0[l] + Up[l]);
         const T fx1 = m1 * kface(ux[1][l], ux[2][l], ux[3][l], ux[4][l], m1);
-        const T n0 = T(0.5) * (Vw0[l] + V00[l]);
         const T fy0 = n0 * kface(uy[0][l], uy[1][l], ux[2][l], uy[2][l], n0);
-        const T n1 = T(0.5) * (Vw1[l] + V01[l]);
         const T fy1 = n1 * kface(uy[1][l], ux[2][l], uy[2][l], uy[3][l], n1);
-        out[l] = -((fx1 - fx0) * rdx + (fy1 - fy0) * rdy + (fz[l + 1] - fz[l]) * rdz[l]);
+        const T sum = (fx1 - fx0) * rdx + (fy1 - fy0) * rdy + (fz[l + 1] - fz[l]) * rdz[l];
+        if constexpr (TR) out[l] = -sum / ju0;
+        else out[l] = -sum;
     }
     ln.store(SU, out);
 }
 
-template <typename T, class Lay, int L>
+template <typename T, class Lay, int L, bool TR>
 __device__ __forceinline__ void slow_sv(const Lane<Lay, L> &ln, T rdx, T rdy, const T (&rdz)[L],
-                                        const T *__restrict__ U, const T *__restrict__ V,
-                                        const T *__restrict__ W, const T *__restrict__ vv,
-                                        T *__restrict__ SV)
+                                        const double *__restrict__ geo, const T *__restrict__ U,
+                                        const T *__restrict__ V, const T *__restrict__ Wz,
+                                        const T *__restrict__ vv, T *__restrict__ SV)
 {
     T vy[5][L], vx[4][L];
 #pragma unroll
@@ -368,8 +438,18 @@ __device__ __forceinline__ void slow_sv(const Lane<Lay, L> &ln, T rdx, T rdy, co
     ln.load(U, 0, 0, U00);
     ln.load(U, 1, -1, Us1);
     ln.load(U, 1, 0, U10);
-    ln.load(W, 0, -1, Wm);
-    ln.load(W, 0, 0, W0);
+    ln.load(Wz, 0, -1, Wm);
+    ln.load(Wz, 0, 0, W0);
+    T jvm = T(1), jv0 = T(1), jvp = T(1), jus0 = T(1), ju00 = T(1), jus1 = T(1), ju10 = T(1);
+    if constexpr (TR) {
+        jvm = (T)ln.geo(geo, GEO_JV, 0, -1);
+        jv0 = (T)ln.geo(geo, GEO_JV, 0, 0);
+        jvp = (T)ln.geo(geo, GEO_JV, 0, 1);
+        jus0 = (T)ln.geo(geo, GEO_JU, 0, -1);
+        ju00 = (T)ln.geo(geo, GEO_JU, 0, 0);
+        jus1 = (T)ln.geo(geo, GEO_JU, 1, -1);
+        ju10 = (T)ln.geo(geo, GEO_JU, 1, 0);
+    }
     T ve[L + 4];
     extend2(vy[2], ve, ln.p, false);
     const bool top = (ln.p == SEG - 1);
@@ -389,24 +469,35 @@ __device__ __forceinline__ void slow_sv(const Lane<Lay, L> &ln, T rdx, T rdy, co
     T out[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) {
-        const T m0 = T(0.5) * (Us0[l] + U00[l]);
+        T m0, m1, n0, n1;
+        if constexpr (TR) {
+            m0 = T(0.5) * (jus0 * Us0[l] + ju00 * U00[l]);
+            m1 = T(0.5) * (jus1 * Us1[l] + ju10 * U10[l]);
+            n0 = T(0.5) * (jvm * Vm[l] + jv0 * V0[l]);
+            n1 = T(0.5) * (jv0 * V0[l] + jvp * Vp[l]);
+        } else {
+            m0 = T(0.5) * (Us0[l] + U00[l]);
+            m1 = T(0.5) * (Us1[l] + U10[l]);
+            n0 = T(0.5) * (Vm[l] + V0[l]);
+            n1 = T(0.5) * (V0[l] + Vp[l]);
+        }
         const T fx0 = m0 * kface(vx[0][l], vx[1][l], vy[2][l], vx[2][l], m0);
-        const T m1 = T(0.5) * (Us1[l] + U10[l]);
         const T fx1 = m1 * kface(vx[1][l], vy[2][l], vx[2][l], vx[3][l], m1);
-        const T n0 = T(0.5) * (Vm[l] + V0[l]);
         const T fy0 = n0 * kface(vy[0][l], vy[1][l], vy[2][l], vy[3][l], n0);
-        const T n1 = T(0.5) * (V0[l] + Vp[l]);
         const T fy1 = n1 * kface(vy[1][l], vy[2][l], vy[3][l], vy[4][l], n1);
-        out[l] = -((fx1 - fx0) * rdx + (fy1 - fy0) * rdy + (fz[l + 1] - fz[l]) * rdz[l]);
+        const T sum = (fx1 - fx0) * rdx + (fy1 - fy0) * rdy + (fz[l + 1] - fz[l]) * rdz[l];
+        if constexpr (TR) out[l] = -sum / jv0;
+        else out[l] = -sum;
     }
     ln.store(SV, out);
 }
 
-template <typename T, class Lay, int L>
+template <typename T, class Lay, int L, bool TR>
 __device__ __forceinline__ void slow_sw(const Lane<Lay, L> &ln, T rdx, T rdy,
-                                        const double *__restrict__ vm, const T *__restrict__ U,
-                                        const T *__restrict__ V, const T *__restrict__ W,
-                                        const T *__restrict__ ww, T *__restrict__ SW)
+                                        const double *__restrict__ vm, const double *__restrict__ geo,
+                                        const T *__restrict__ U, const T *__restrict__ V,
+                                        const T *__restrict__ Wz, const T *__restrict__ ww,
+                                        T *__restrict__ SW)
 {
     T wx[5][L], wy[4][L];
 #pragma unroll
@@ -420,7 +511,7 @@ __device__ __forceinline__ void slow_sw(const Lane<Lay, L> &ln, T rdx, T rdy,
     ln.load(U, 1, 0, U1);
     ln.load(V, 0, 0, V0);
     ln.load(V, 0, 1, V1);
-    ln.load(W, 0, 0, W0);
+    ln.load(Wz, 0, 0, W0);
     // level below the lane's first level (unused on the bottom level face)
     const T U0b = from_below(U0[L - 1]), U1b = from_below(U1[L - 1]);
     const T V0b = from_below(V0[L - 1]), V1b = from_below(V1[L - 1]);
@@ -429,6 +520,14 @@ __device__ __forceinline__ void slow_sw(const Lane<Lay, L> &ln, T rdx, T rdy,
     extend2(W0, We, ln.p, true);
     T rdzf[L];
     ln.vmet(vm, VM_RDZF, rdzf);
+    T ju0 = T(1), ju1 = T(1), jv0 = T(1), jv1 = T(1), jc = T(1);
+    if constexpr (TR) {
+        ju0 = (T)ln.geo(geo, GEO_JU, 0, 0);
+        ju1 = (T)ln.geo(geo, GEO_JU, 1, 0);
+        jv0 = (T)ln.geo(geo, GEO_JV, 0, 0);
+        jv1 = (T)ln.geo(geo, GEO_JV, 0, 1);
+        jc = (T)ln.geo(geo, GEO_J, 0, 0);
+    }
     // vertical fluxes at the cell centres cc = k0-1 .. k0+L-1
     T fz[L + 1];
 #pragma unroll
@@ -444,25 +543,37 @@ __device__ __forceinline__ void slow_sw(const Lane<Lay, L> &ln, T rdx, T rdy,
         const T u1b = (l == 0) ? U1b : U1[l - 1];
         const T v0b = (l == 0) ? V0b : V0[l - 1];
         const T v1b = (l == 0) ? V1b : V1[l - 1];
-        const T m0 = T(0.5) * (u0b + U0[l]);
+        T m0, m1, n0, n1;
+        if constexpr (TR) {
+            m0 = T(0.5) * (ju0 * u0b + ju0 * U0[l]);
+            m1 = T(0.5) * (ju1 * u1b + ju1 * U1[l]);
+            n0 = T(0.5) * (jv0 * v0b + jv0 * V0[l]);
+            n1 = T(0.5) * (jv1 * v1b + jv1 * V1[l]);
+        } else {
+            m0 = T(0.5) * (u0b + U0[l]);
+            m1 = T(0.5) * (u1b + U1[l]);
+            n0 = T(0.5) * (v0b + V0[l]);
+            n1 = T(0.5) * (v1b + V1[l]);
+        }
         const T fx0 = m0 * kface(wx[0][l], wx[1][l], wx[2][l], wx[3][l], m0);
-        const T m1 = T(0.5) * (u1b + U1[l]);
         const T fx1 = m1 * kface(wx[1][l], wx[2][l], wx[3][l], wx[4][l], m1);
-        const T n0 = T(0.5) * (v0b + V0[l]);
         const T fy0 = n0 * kface(wy[0][l], wy[1][l], wx[2][l], wy[2][l], n0);
-        const T n1 = T(0.5) * (v1b + V1[l]);
         const T fy1 = n1 * kface(wy[1][l], wx[2][l], wy[2][l], wy[3][l], n1);
-        const T s = -((fx1 - fx0) * rdx + (fy1 - fy0) * rdy + (fz[l + 1] - fz[l]) * rdzf[l]);
+        const T sum = (fx1 - fx0) * rdx + (fy1 - fy0) * rdy + (fz[l + 1] - fz[l]) * rdzf[l];
+        T s;
+        if constexpr (TR) s = -sum / jc;
+        else s = -sum;
         out[l] = (k == 0) ? T(0) : s;
     }
     ln.store(SW, out);
 }
 
-template <typename T, class Lay, int L>
+template <typename T, class Lay, int L, bool TR>
 __device__ __forceinline__ void slow_rt(const Lane<Lay, L> &ln, T rdx, T rdy, const T (&rdz)[L],
-                                        const double *__restrict__ vm, const T *__restrict__ U,
-                                        const T *__restrict__ V, const T *__restrict__ W,
-                                        const T *__restrict__ th, T *__restrict__ RT)
+                                        const double *__restrict__ vm, const double *__restrict__ geo,
+                                        const T *__restrict__ U, const T *__restrict__ V,
+                                        const T *__restrict__ Wz, const T *__restrict__ th,
+                                        T *__restrict__ RT)
 {
     T tx[5][L], ty[4][L];
 #pragma unroll
@@ -476,7 +587,15 @@ __device__ __forceinline__ void slow_rt(const Lane<Lay, L> &ln, T rdx, T rdy, co
     ln.load(U, 1, 0, U1);
     ln.load(V, 0, 0, V0);
     ln.load(V, 0, 1, V1);
-    ln.load(W, 0, 0, W0);
+    ln.load(Wz, 0, 0, W0);
+    T ju0 = T(1), ju1 = T(1), jv0 = T(1), jv1 = T(1), jc = T(1);
+    if constexpr (TR) {
+        ju0 = (T)ln.geo(geo, GEO_JU, 0, 0);
+        ju1 = (T)ln.geo(geo, GEO_JU, 1, 0);
+        jv0 = (T)ln.geo(geo, GEO_JV, 0, 0);
+        jv1 = (T)ln.geo(geo, GEO_JV, 0, 1);
+        jc = (T)ln.geo(geo, GEO_J, 0, 0);
+    }
     T te[L + 4];
     extend2(tx[2], te, ln.p, false);
     const bool top = (ln.p == SEG - 1);
@@ -502,50 +621,57 @@ __device__ __forceinline__ void slow_rt(const Lane<Lay, L> &ln, T rdx, T rdy, co
     T out[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) {
-        const T m0 = U0[l];
+        T m0 = U0[l], m1 = U1[l], n0 = V0[l], n1 = V1[l];
+        if constexpr (TR) {
+            m0 = ju0 * m0;
+            m1 = ju1 * m1;
+            n0 = jv0 * n0;
+            n1 = jv1 * n1;
+        }
         const T g0 = m0 * (kface(tx[0][l], tx[1][l], tx[2][l], tx[3][l], m0) -
                            T(0.5) * (tx[1][l] + tx[2][l]));
-        const T m1 = U1[l];
         const T g1 = m1 * (kface(tx[1][l], tx[2][l], tx[3][l], tx[4][l], m1) -
                            T(0.5) * (tx[2][l] + tx[3][l]));
-        const T n0 = V0[l];
         const T h0 = n0 * (kface(ty[0][l], ty[1][l], tx[2][l], ty[2][l], n0) -
                            T(0.5) * (ty[1][l] + tx[2][l]));
-        const T n1 = V1[l];
         const T h1 = n1 * (kface(ty[1][l], tx[2][l], ty[2][l], ty[3][l], n1) -
                            T(0.5) * (tx[2][l] + ty[2][l]));
-        out[l] = -((g1 - g0) * rdx + (h1 - h0) * rdy + (gz[l + 1] - gz[l]) * rdz[l]);
+        const T sum = (g1 - g0) * rdx + (h1 - h0) * rdy + (gz[l + 1] - gz[l]) * rdz[l];
+        if constexpr (TR) out[l] = -sum / jc;
+        else out[l] = -sum;
     }
     ln.store(RT, out);
 }
 
-template <typename T, class Lay, int L>
-__global__ __launch_bounds__(BLOCK) void k_slow_flux(Group gr, int stage, int n_short)
+template <typename T, class Lay, int L, bool TR>
+__device__ __forceinline__ void flux_body(
+    const Lane<Lay, L> &ln, const double *__restrict__ vm, const double *__restrict__ geo, T rdx,
+    T rdy, const T *__restrict__ U, const T *__restrict__ V, const T *__restrict__ Wz,
+    const T *__restrict__ uu, const T *__restrict__ vv, const T *__restrict__ ww,
+    const T *__restrict__ th, T *__restrict__ SU, T *__restrict__ SV, T *__restrict__ SW,
+    T *__restrict__ RT)
+{
+    T rdz[L];
+    ln.vmet(vm, VM_RDZ, rdz);
+    slow_su<T, Lay, L, TR>(ln, rdx, rdy, rdz, geo, U, V, Wz, uu, SU);
+    slow_sv<T, Lay, L, TR>(ln, rdx, rdy, rdz, geo, U, V, Wz, vv, SV);
+    slow_sw<T, Lay, L, TR>(ln, rdx, rdy, vm, geo, U, V, Wz, ww, SW);
+    slow_rt<T, Lay, L, TR>(ln, rdx, rdy, rdz, vm, geo, U, V, Wz, th, RT);
+}
+
+template <typename T, class Lay, int L, bool TR>
+__global__ __launch_bounds__(BLOCK) void k_slow_flux(Group gr)
 {
     const Where wh = locate(gr);
     if (!wh.active) return;
     const MemberDev *m = wh.m;
     const Lane<Lay, L> ln(m->nx, m->ny, m->nz, wh.i, wh.j);
-    const double *__restrict__ vm = m->vm;
-    void *const *in = m->st[stage_input(m, stage, n_short)];
-    const T *__restrict__ U = (const T *)in[1];
-    const T *__restrict__ V = (const T *)in[2];
-    const T *__restrict__ W = (const T *)in[3];
-    const T *__restrict__ uu = (const T *)m->spec[0];
-    const T *__restrict__ vv = (const T *)m->spec[1];
-    const T *__restrict__ ww = (const T *)m->spec[2];
-    const T *__restrict__ th = (const T *)m->slow[4];
-    T *__restrict__ SU = (T *)m->slow[0];
-    T *__restrict__ SV = (T *)m->slow[1];
-    T *__restrict__ SW = (T *)m->slow[2];
-    T *__restrict__ RT = (T *)m->slow[3];
-    const T rdx = (T)m->rdx, rdy = (T)m->rdy;
-    T rdz[L];
-    ln.vmet(vm, VM_RDZ, rdz);
-    slow_su(ln, rdx, rdy, rdz, U, V, W, uu, SU);
-    slow_sv(ln, rdx, rdy, rdz, U, V, W, vv, SV);
-    slow_sw(ln, rdx, rdy, vm, U, V, W, ww, SW);
-    slow_rt(ln, rdx, rdy, rdz, vm, U, V, W, th, RT);
+    flux_body<T, Lay, L, TR>(ln, m->vm, m->geo, (T)m->rdx, (T)m->rdy, (const T *)buf(m, gr.src, 1),
+                             (const T *)buf(m, gr.src, 2),
+                             TR ? (const T *)m->spec[3] : (const T *)buf(m, gr.src, 3),
+                             (const T *)m->spec[0], (const T *)m->spec[1], (const T *)m->spec[2],
+                             (const T *)m->slow[4], (T *)m->slow[0], (T *)m->slow[1],
+                             (T *)m->slow[2], (T *)m->slow[3]);
 }
 
 // --------------------------------------------------------------------------
@@ -619,38 +745,51 @@ __device__ __forceinline__ void segment_solve(int p, const S (&A)[L], const S (&
     x[L - 1] = X;
 }
 
-template <typename T, typename S, class Lay, int L>
-__global__ __launch_bounds__(BLOCK) void k_short_step(Group gr, int stage, int sub, int n_short)
+// Occupancy target of the short step (waves per SIMD), chosen so that the
+// register budget holds the lane's levels without spilling: 4 in float32
+// (3 with the terrain terms), 2 with a float64 solve (1 for float64 storage
+// with the terrain terms), 1 for 8 levels per lane.
+template <typename T, typename S, int L, bool TR>
+constexpr int short_waves()
 {
-    const Where wh = locate(gr);
-    if (!wh.active) return;
-    const MemberDev *m = wh.m;
-    const Lane<Lay, L> ln(m->nx, m->ny, m->nz, wh.i, wh.j);
-    const double *__restrict__ vm = m->vm;
-    const int src = sub == 0 ? m->roles[0] : m->roles[1 + ((sub - 1) & 1)];
-    const int dst = m->roles[1 + (sub & 1)];
-    void *const *in = m->st[src];
-    void *const *out = m->st[dst];
-    const T *__restrict__ rp = (const T *)in[0];
-    const T *__restrict__ U = (const T *)in[1];
-    const T *__restrict__ V = (const T *)in[2];
-    const T *__restrict__ W = (const T *)in[3];
-    const T *__restrict__ tp = (const T *)in[4];
-    T *__restrict__ rpo = (T *)out[0];
-    T *__restrict__ Uo = (T *)out[1];
-    T *__restrict__ Vo = (T *)out[2];
-    T *__restrict__ Wo = (T *)out[3];
-    T *__restrict__ tpo = (T *)out[4];
-    const T *__restrict__ SU = (const T *)m->slow[0];
-    const T *__restrict__ SV = (const T *)m->slow[1];
-    const T *__restrict__ SW = (const T *)m->slow[2];
-    const T *__restrict__ RT = (const T *)m->slow[3];
-    const T *__restrict__ ths = (const T *)m->slow[4];
-    const T *__restrict__ P0 = (const T *)m->slow[5];
-    const T *__restrict__ Cs = (const T *)m->slow[6];
-    const double frac = stage == 0 ? 1.0 / 3.0 : (stage == 1 ? 0.5 : 1.0);
-    const double dtau_d = m->dt * frac / n_short;
-    const T dt = (T)dtau_d, rdx = (T)m->rdx, rdy = (T)m->rdy;
+    if (L >= 8) return 1;
+    if (sizeof(T) == 4 && sizeof(S) == 4) return TR ? 3 : 4;
+    if (sizeof(T) == 8 && TR && L >= 4) return 1;
+    return 2;
+}
+
+// d p / d zeta at the lane's cell centres from a column's p: the mean of the
+// differences over the two level faces of the cell, the one inner face at the
+// lowest and highest cell.  rdzf[l] = 1/dzf of face k0+l.
+template <typename T, int L>
+__device__ __forceinline__ void ddzeta(const T (&pp)[L], const T (&rdzf)[L], int p, int k0, int nz,
+                                       T (&g)[L])
+{
+    T dn[L];
+    const T pb = from_below(pp[L - 1]);
+#pragma unroll
+    for (int l = 0; l < L; ++l) dn[l] = (pp[l] - ((l == 0) ? pb : pp[l - 1])) * rdzf[l];
+    const T dna = from_above(dn[0]);
+    (void)p;
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        const int k = k0 + l;
+        const T up = (l < L - 1) ? dn[l + 1] : dna;
+        g[l] = (k == 0) ? up : ((k == nz - 1) ? dn[l] : T(0.5) * (dn[l] + up));
+    }
+}
+
+template <typename T, typename S, class Lay, int L, bool TR>
+__device__ __forceinline__ void short_body(
+    const Lane<Lay, L> &ln, const double *__restrict__ vm, const double *__restrict__ geo,
+    double dtau_d, double beta_d, T rdx, T rdy,
+    const T *__restrict__ rp, const T *__restrict__ U, const T *__restrict__ V,
+    const T *__restrict__ W, const T *__restrict__ tp, T *__restrict__ rpo, T *__restrict__ Uo,
+    T *__restrict__ Vo, T *__restrict__ Wo, T *__restrict__ tpo, const T *__restrict__ SU,
+    const T *__restrict__ SV, const T *__restrict__ SW, const T *__restrict__ RT,
+    const T *__restrict__ ths, const T *__restrict__ P0, const T *__restrict__ Cs)
+{
+    const T dt = (T)dtau_d;
 
     // ---- horizontally explicit part (storage precision) ----
     T pc[L], pw[L], pe[L], ps[L], pn[L];
@@ -675,6 +814,43 @@ __global__ __launch_bounds__(BLOCK) void k_short_step(Group gr, int stage, int s
 #pragma unroll
         for (int l = 0; l < L; ++l) pn[l] = a[l] + c[l] * t[l];
     }
+    // over terrain: metric correction (z_x/J) dp'/dzeta of the four faces
+    T cw[L], ce[L], cs[L], cn[L];
+    T ju0 = T(1), ju1 = T(1), jv0 = T(1), jv1 = T(1), rjc = T(1);
+    T su0 = T(0), su1 = T(0), sv0 = T(0), sv1 = T(0);
+    double jcol = 1.0;
+    if constexpr (TR) {
+        ju0 = (T)ln.geo(geo, GEO_JU, 0, 0);
+        ju1 = (T)ln.geo(geo, GEO_JU, 1, 0);
+        jv0 = (T)ln.geo(geo, GEO_JV, 0, 0);
+        jv1 = (T)ln.geo(geo, GEO_JV, 0, 1);
+        su0 = (T)ln.geo(geo, GEO_SU, 0, 0);
+        su1 = (T)ln.geo(geo, GEO_SU, 1, 0);
+        sv0 = (T)ln.geo(geo, GEO_SV, 0, 0);
+        sv1 = (T)ln.geo(geo, GEO_SV, 0, 1);
+        jcol = ln.geo(geo, GEO_J, 0, 0);
+        rjc = T(1) / (T)jcol;
+        T rdzf_t[L], dc[L];
+        ln.vmet(vm, VM_RDZF, rdzf_t);
+        ln.vmet(vm, VM_DC, dc);
+        T gc[L], g1[L], g2[L];
+        ddzeta(pc, rdzf_t, ln.p, ln.k0, ln.nz, gc);
+        ddzeta(pw, rdzf_t, ln.p, ln.k0, ln.nz, g1);
+        ddzeta(pe, rdzf_t, ln.p, ln.k0, ln.nz, g2);
+        const T fw = su0 / ju0, fe = su1 / ju1, fs = sv0 / jv0, fn = sv1 / jv1;
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            cw[l] = (dc[l] * fw) * (T(0.5) * (g1[l] + gc[l]));
+            ce[l] = (dc[l] * fe) * (T(0.5) * (gc[l] + g2[l]));
+        }
+        ddzeta(ps, rdzf_t, ln.p, ln.k0, ln.nz, g1);
+        ddzeta(pn, rdzf_t, ln.p, ln.k0, ln.nz, g2);
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            cs[l] = (dc[l] * fs) * (T(0.5) * (g1[l] + gc[l]));
+            cn[l] = (dc[l] * fn) * (T(0.5) * (gc[l] + g2[l]));
+        }
+    }
     T thc[L], thw[L], the[L], tsth[L], tnth[L];
     ln.load(ths, 0, 0, thc);
     ln.load(ths, -1, 0, thw);
@@ -696,17 +872,30 @@ __global__ __launch_bounds__(BLOCK) void k_short_step(Group gr, int stage, int s
     ln.template load<true>(SW, 0, 0, SWc);
     ln.template load<true>(RT, 0, 0, RTc);
 
-    T Up[L], Vp[L], rt[L], tt[L];
+    T Up[L], Vp[L], rt[L], tt[L], mx[L], my[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) {
-        const T up0 = U0[l] + dt * (SU0[l] - (pc[l] - pw[l]) * rdx);
-        const T up1 = U1[l] + dt * (SU1[l] - (pe[l] - pc[l]) * rdx);
-        const T vp0 = V0[l] + dt * (SV0[l] - (pc[l] - ps[l]) * rdy);
-        const T vp1 = V1[l] + dt * (SV1[l] - (pn[l] - pc[l]) * rdy);
-        const T div = (up1 - up0) * rdx + (vp1 - vp0) * rdy;
+        T up0, up1, vp0, vp1, div, tdiv;
         const T fw = T(0.5) * (thw[l] + thc[l]), fe = T(0.5) * (thc[l] + the[l]);
         const T fs = T(0.5) * (tsth[l] + thc[l]), fn = T(0.5) * (thc[l] + tnth[l]);
-        const T tdiv = (fe * up1 - fw * up0) * rdx + (fn * vp1 - fs * vp0) * rdy;
+        if constexpr (TR) {
+            up0 = U0[l] + dt * (SU0[l] - ((pc[l] - pw[l]) * rdx - cw[l]));
+            up1 = U1[l] + dt * (SU1[l] - ((pe[l] - pc[l]) * rdx - ce[l]));
+            vp0 = V0[l] + dt * (SV0[l] - ((pc[l] - ps[l]) * rdy - cs[l]));
+            vp1 = V1[l] + dt * (SV1[l] - ((pn[l] - pc[l]) * rdy - cn[l]));
+            const T mu0 = ju0 * up0, mu1 = ju1 * up1, mv0 = jv0 * vp0, mv1 = jv1 * vp1;
+            div = ((mu1 - mu0) * rdx + (mv1 - mv0) * rdy) * rjc;
+            tdiv = ((fe * mu1 - fw * mu0) * rdx + (fn * mv1 - fs * mv0) * rdy) * rjc;
+            mx[l] = T(0.5) * (su0 * up0 + su1 * up1);
+            my[l] = T(0.5) * (sv0 * vp0 + sv1 * vp1);
+        } else {
+            up0 = U0[l] + dt * (SU0[l] - (pc[l] - pw[l]) * rdx);
+            up1 = U1[l] + dt * (SU1[l] - (pe[l] - pc[l]) * rdx);
+            vp0 = V0[l] + dt * (SV0[l] - (pc[l] - ps[l]) * rdy);
+            vp1 = V1[l] + dt * (SV1[l] - (pn[l] - pc[l]) * rdy);
+            div = (up1 - up0) * rdx + (vp1 - vp0) * rdy;
+            tdiv = (fe * up1 - fw * up0) * rdx + (fn * vp1 - fs * vp0) * rdy;
+        }
         Up[l] = up0;
         Vp[l] = vp0;
         rt[l] = rpc[l] - dt * div;
@@ -716,7 +905,7 @@ __global__ __launch_bounds__(BLOCK) void k_short_step(Group gr, int stage, int s
     ln.store(Vo, Vp);
 
     // ---- vertically implicit part (solve precision S) ----
-    const S be = (S)m->beta, dts = (S)dtau_d;
+    const S be = (S)beta_d, dts = (S)dtau_d;
     const S one_m_be = S(1) - be;
     const S mu = be * be * dts * dts;
     const S grav = (S)kGrav;
@@ -727,6 +916,29 @@ __global__ __launch_bounds__(BLOCK) void k_short_step(Group gr, int stage, int s
     ln.vmet(vm, VM_RDZF, rdzf);
     ln.vmet(vm, VM_A, av);
     ln.vmet(vm, VM_B, bv);
+    // over terrain: the slope part E of Omega on the lane's level faces (from
+    // the new horizontal momentum), and thicknesses J dzeta
+    S Ef[L + 1];
+    if constexpr (TR) {
+        const S rj = S(1) / (S)jcol;
+        S df[L];
+        ln.vmet(vm, VM_DF, df);
+        const S mxb = (S)from_below(mx[L - 1]), myb = (S)from_below(my[L - 1]);
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            const int k = ln.k0 + l;
+            const S mxm = (l == 0) ? mxb : (S)mx[l - 1];
+            const S mym = (l == 0) ? myb : (S)my[l - 1];
+            const S e = df[l] * ((av[l] * (S)mx[l] + bv[l] * mxm) + (av[l] * (S)my[l] + bv[l] * mym));
+            Ef[l] = (k == 0) ? S(0) : e;
+            rdz[l] = rdz[l] * rj;
+            rdzf[l] = rdzf[l] * rj;
+        }
+        const S ea = from_above(Ef[0]);
+        Ef[L] = top ? S(0) : ea;
+    } else {
+        (void)mx; (void)my;
+    }
     const S rdz_b = from_below(rdz[L - 1]);   // 1/dz of the level below the lane
 
     // theta_s on the lane's level faces k0..k0+L-1, and on face k0+L
@@ -754,6 +966,11 @@ __global__ __launch_bounds__(BLOCK) void k_short_step(Group gr, int stage, int s
         const S f = one_m_be * dts * rdz[l];
         thE[l] = (S)tt[l] - f * (thf[l + 1] * Wf[l + 1] - thf[l] * Wf[l]);
         rhE[l] = (S)rt[l] - f * (Wf[l + 1] - Wf[l]);
+        if constexpr (TR) {
+            const S g = dts * rdz[l];
+            thE[l] = thE[l] + g * (thf[l + 1] * Ef[l + 1] - thf[l] * Ef[l]);
+            rhE[l] = rhE[l] + g * (Ef[l + 1] - Ef[l]);
+        }
         Cc[l] = (S)Csc[l];
         pE[l] = be * ((S)P0c[l] + Cc[l] * thE[l]) + one_m_be * (S)pc[l];
         rEs[l] = be * rhE[l] + one_m_be * (S)rpc[l];
@@ -802,6 +1019,24 @@ __global__ __launch_bounds__(BLOCK) void k_short_step(Group gr, int stage, int s
     ln.store(tpo, tpn);
 }
 
+template <typename T, typename S, class Lay, int L, bool TR>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(short_waves<T, S, L, TR>())))
+void k_short_step(Group gr, double frac)
+{
+    const Where wh = locate(gr);
+    if (!wh.active) return;
+    const MemberDev *m = wh.m;
+    const Lane<Lay, L> ln(m->nx, m->ny, m->nz, wh.i, wh.j);
+    short_body<T, S, Lay, L, TR>(
+        ln, m->vm, m->geo, m->dt * frac, m->beta, (T)m->rdx, (T)m->rdy,
+        (const T *)buf(m, gr.src, 0), (const T *)buf(m, gr.src, 1), (const T *)buf(m, gr.src, 2),
+        (const T *)buf(m, gr.src, 3), (const T *)buf(m, gr.src, 4), (T *)buf(m, gr.dst, 0),
+        (T *)buf(m, gr.dst, 1), (T *)buf(m, gr.dst, 2), (T *)buf(m, gr.dst, 3),
+        (T *)buf(m, gr.dst, 4), (const T *)m->slow[0], (const T *)m->slow[1],
+        (const T *)m->slow[2], (const T *)m->slow[3], (const T *)m->slow[4],
+        (const T *)m->slow[5], (const T *)m->slow[6]);
+}
+
 // --------------------------------------------------------------------------
 // float64 sums with a fixed two-level order
 // --------------------------------------------------------------------------
@@ -821,24 +1056,26 @@ __device__ __forceinline__ double block_sum(double v, double *sh)
 // Partial sums of one member: its partial block q accumulates the member's
 // 16x1 tiles q, q + P, q + 2P, ... (P = its partial count) in that order, each
 // lane in float64, then a fixed tree over the block.  The launch covers the
-// partial blocks of every member of a group (gr.prefix over partial counts).
-template <typename T, class Lay, int L, bool ENERGY>
+// partial blocks of every member of a group (gr.blk maps blocks to partials).
+template <typename T, class Lay, int L, bool ENERGY, bool TR>
 __global__ __launch_bounds__(BLOCK) void k_sum_partial(Group gr)
 {
     __shared__ double sh[BLOCK];
-    const int b = (int)blockIdx.x;
-    int lo = 0, hi = gr.nm;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (gr.prefix[mid] <= b) lo = mid;
-        else hi = mid;
+    int q = (int)blockIdx.x, id = gr.first;
+    if (gr.nm > 1) {
+        const unsigned v = gr.blk[blockIdx.x];
+        q = (int)(v & 0xFFFFFFu);
+        id = (int)(v >> 24);
     }
-    const MemberDev *m = gr.mem + gr.ids[lo];
-    const int q = b - gr.prefix[lo];
+    const MemberDev *m = gr.mem + id;
     const int tiles_x = (m->nx + kColsPerBlock - 1) / kColsPerBlock;
     const int ntiles = tiles_x * m->ny;
     const double *__restrict__ vm = m->vm;
-    void *const *st = m->st[m->roles[0]];
+    const T *__restrict__ s0 = (const T *)buf(m, gr.src, 0);
+    const T *__restrict__ s1 = (const T *)buf(m, gr.src, 1);
+    const T *__restrict__ s2 = (const T *)buf(m, gr.src, 2);
+    const T *__restrict__ s3 = (const T *)buf(m, gr.src, 3);
+    const T *__restrict__ s4 = (const T *)buf(m, gr.src, 4);
     double acc = 0.0;
     for (int t = q; t < ntiles; t += m->npart) {
         const int i = (t % tiles_x) * kColsPerBlock + (int)threadIdx.x / SEG;
@@ -847,26 +1084,51 @@ __global__ __launch_bounds__(BLOCK) void k_sum_partial(Group gr)
             const Lane<Lay, L> ln(m->nx, m->ny, m->nz, i, j);
             double vol[L];
             ln.vmet(vm, VM_VOL, vol);
+            if constexpr (TR) {
+                // cell volume J dx dy dzeta
+                const double jc = ln.geo(m->geo, GEO_J, 0, 0);
+#pragma unroll
+                for (int l = 0; l < L; ++l) vol[l] = vol[l] * jc;
+            }
             if constexpr (!ENERGY) {
                 T r[L];
-                ln.template load<true>((const T *)st[0], 0, 0, r);
+                ln.template load<true>(s0, 0, 0, r);
 #pragma unroll
                 for (int l = 0; l < L; ++l) acc += (double)r[l] * vol[l];
             } else {
                 T r[L], u0[L], u1[L], v0[L], v1[L], w0[L], th[L];
-                ln.load((const T *)st[0], 0, 0, r);
-                ln.load((const T *)st[1], 0, 0, u0);
-                ln.load((const T *)st[1], 1, 0, u1);
-                ln.load((const T *)st[2], 0, 0, v0);
-                ln.load((const T *)st[2], 0, 1, v1);
-                ln.load((const T *)st[3], 0, 0, w0);
-                ln.load((const T *)st[4], 0, 0, th);
+                ln.load(s0, 0, 0, r);
+                ln.load(s1, 0, 0, u0);
+                ln.load(s1, 1, 0, u1);
+                ln.load(s2, 0, 0, v0);
+                ln.load(s2, 0, 1, v1);
+                ln.load(s3, 0, 0, w0);
+                ln.load(s4, 0, 0, th);
                 const T wt = from_above(w0[0]);
                 double rref[L], rtref[L], pref[L], zc[L];
-                ln.vmet(vm, VM_RHO, rref);
-                ln.vmet(vm, VM_RT, rtref);
-                ln.vmet(vm, VM_P, pref);
                 ln.vmet(vm, VM_ZC, zc);
+                if constexpr (TR) {
+                    T a[L];
+                    ln.load((const T *)m->ref[0], 0, 0, a);
+#pragma unroll
+                    for (int l = 0; l < L; ++l) rref[l] = (double)a[l];
+                    ln.load((const T *)m->ref[1], 0, 0, a);
+#pragma unroll
+                    for (int l = 0; l < L; ++l) rtref[l] = (double)a[l];
+                    ln.load((const T *)m->ref[2], 0, 0, a);
+#pragma unroll
+                    for (int l = 0; l < L; ++l) pref[l] = (double)a[l];
+                    // true height of the cell centre
+                    double dc[L];
+                    ln.vmet(vm, VM_DC, dc);
+                    const double h = ln.geo(m->geo, GEO_H, 0, 0);
+#pragma unroll
+                    for (int l = 0; l < L; ++l) zc[l] = zc[l] + h * dc[l];
+                } else {
+                    ln.vmet(vm, VM_RHO, rref);
+                    ln.vmet(vm, VM_RT, rtref);
+                    ln.vmet(vm, VM_P, pref);
+                }
 #pragma unroll
                 for (int l = 0; l < L; ++l) {
                     const double rho = rref[l] + (double)r[l];
@@ -890,7 +1152,7 @@ __global__ __launch_bounds__(BLOCK) void k_sum_partial(Group gr)
 __global__ __launch_bounds__(BLOCK) void k_sum_final(Group gr, int slot)
 {
     __shared__ double sh[BLOCK];
-    const MemberDev *m = gr.mem + gr.ids[blockIdx.x];
+    const MemberDev *m = gr.mem + (gr.nm == 1 ? gr.first : gr.ids[blockIdx.x]);
     double s = 0.0, c = 0.0;
     for (int q = threadIdx.x; q < m->npart; q += BLOCK) {
         const double x = m->partials[q];
@@ -900,25 +1162,6 @@ __global__ __launch_bounds__(BLOCK) void k_sum_final(Group gr, int slot)
     }
     const double tot = block_sum(s + c, sh);
     if (threadIdx.x == 0) m->sums[slot] = tot;
-}
-
-__global__ void k_set_dt(MemberDev *mem, int q, double dt)
-{
-    if (threadIdx.x == 0) mem[q].dt = dt;
-}
-
-// The long step's result (written by the last short step of stage 3) becomes
-// the start buffer of the next long step.
-__global__ void k_rotate(MemberDev *mem, int n, int n_short)
-{
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n) return;
-    MemberDev *m = mem + q;
-    const int cur = m->roles[1 + ((n_short - 1) & 1)];
-    const int a = m->roles[0], b = m->roles[1 + (n_short & 1)];
-    m->roles[0] = cur;
-    m->roles[1] = a;
-    m->roles[2] = b;
 }
 
 // --------------------------------------------------------------------------
@@ -950,42 +1193,56 @@ hipError_t dispatch(int prec, int layout, int L, Args &&...args)
 
 template <typename T, typename S, class Lay, int L>
 struct RunPrep {
-    static hipError_t run(const Group &gr, int stage, int n_short, hipStream_t s)
+    static hipError_t run(const Group &gr, hipStream_t s)
     {
-        hipLaunchKernelGGL((k_slow_prep<T, Lay, L>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr, stage,
-                           n_short);
+        if (gr.terrain)
+            hipLaunchKernelGGL((k_slow_prep<T, Lay, L, true>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr);
+        else
+            hipLaunchKernelGGL((k_slow_prep<T, Lay, L, false>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr);
         return hipGetLastError();
     }
 };
 
 template <typename T, typename S, class Lay, int L>
 struct RunFlux {
-    static hipError_t run(const Group &gr, int stage, int n_short, hipStream_t s)
+    static hipError_t run(const Group &gr, hipStream_t s)
     {
-        hipLaunchKernelGGL((k_slow_flux<T, Lay, L>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr, stage,
-                           n_short);
+        if (gr.terrain)
+            hipLaunchKernelGGL((k_slow_flux<T, Lay, L, true>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr);
+        else
+            hipLaunchKernelGGL((k_slow_flux<T, Lay, L, false>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr);
         return hipGetLastError();
     }
 };
 
 template <typename T, typename S, class Lay, int L>
 struct RunShort {
-    static hipError_t run(const Group &gr, int stage, int sub, int n_short, hipStream_t s)
+    static hipError_t run(const Group &gr, double frac, hipStream_t s)
     {
-        hipLaunchKernelGGL((k_short_step<T, S, Lay, L>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr,
-                           stage, sub, n_short);
+        if (gr.terrain)
+            hipLaunchKernelGGL((k_short_step<T, S, Lay, L, true>), dim3(gr.nblocks), dim3(BLOCK), 0,
+                               s, gr, frac);
+        else
+            hipLaunchKernelGGL((k_short_step<T, S, Lay, L, false>), dim3(gr.nblocks), dim3(BLOCK), 0,
+                               s, gr, frac);
         return hipGetLastError();
     }
 };
 
 template <typename T, typename S, class Lay, int L>
 struct RunSums {
-    static hipError_t run(const Group &gr, bool energy, hipStream_t s)
+    template <bool TR>
+    static void partial(const Group &gr, bool energy, hipStream_t s)
     {
         if (energy)
-            hipLaunchKernelGGL((k_sum_partial<T, Lay, L, true>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr);
+            hipLaunchKernelGGL((k_sum_partial<T, Lay, L, true, TR>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr);
         else
-            hipLaunchKernelGGL((k_sum_partial<T, Lay, L, false>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr);
+            hipLaunchKernelGGL((k_sum_partial<T, Lay, L, false, TR>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr);
+    }
+    static hipError_t run(const Group &gr, bool energy, hipStream_t s)
+    {
+        if (gr.terrain) partial<true>(gr, energy, s);
+        else partial<false>(gr, energy, s);
         hipLaunchKernelGGL(k_sum_final, dim3(gr.nm), dim3(BLOCK), 0, s, gr, energy ? 1 : 0);
         return hipGetLastError();
     }
@@ -993,39 +1250,24 @@ struct RunSums {
 
 }  // namespace
 
-hipError_t launch_slow_prep(int prec, int layout, int L, const Group &gr, int stage, int n_short,
-                            hipStream_t s)
+hipError_t launch_slow_prep(int prec, int layout, int L, const Group &gr, hipStream_t s)
 {
-    return dispatch<RunPrep>(prec, layout, L, gr, stage, n_short, s);
+    return dispatch<RunPrep>(prec, layout, L, gr, s);
 }
 
-hipError_t launch_slow_flux(int prec, int layout, int L, const Group &gr, int stage, int n_short,
-                            hipStream_t s)
+hipError_t launch_slow_flux(int prec, int layout, int L, const Group &gr, hipStream_t s)
 {
-    return dispatch<RunFlux>(prec, layout, L, gr, stage, n_short, s);
+    return dispatch<RunFlux>(prec, layout, L, gr, s);
 }
 
-hipError_t launch_short_step(int prec, int layout, int L, const Group &gr, int stage, int sub,
-                             int n_short, hipStream_t s)
+hipError_t launch_short_step(int prec, int layout, int L, const Group &gr, double frac, hipStream_t s)
 {
-    return dispatch<RunShort>(prec, layout, L, gr, stage, sub, n_short, s);
+    return dispatch<RunShort>(prec, layout, L, gr, frac, s);
 }
 
 hipError_t launch_sums(int prec, int layout, int L, const Group &gr, bool energy, hipStream_t s)
 {
     return dispatch<RunSums>(prec, layout, L, gr, energy, s);
-}
-
-hipError_t launch_set_dt(MemberDev *mem, int q, double dt, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(64), 0, s, mem, q, dt);
-    return hipGetLastError();
-}
-
-hipError_t launch_rotate(MemberDev *mem, int n, int n_short, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_rotate, dim3((n + 63) / 64), dim3(64), 0, s, mem, n, n_short);
-    return hipGetLastError();
 }
 
 }  // namespace hv

@@ -2,15 +2,17 @@
 //
 // A grid is an ensemble of one member.  An ensemble keeps, inside the
 // caller's workspace, a device table with one record per member (sizes,
-// spacings, long-step length, buffer roles and array pointers) and, per group
-// of members with the same nz, the member ids and block prefix sums each
-// grouped launch uses.  One long step is the launch sequence
+// spacings, long-step length and array pointers) and, per group of members
+// with the same nz, the member ids and a per-block (member, tile) map each
+// grouped launch uses; a single member's record travels in the kernel
+// arguments instead.  One long step is the launch sequence
 //   for each stage: slow prep, slow flux, n short steps   (per group)
-//   rotate buffer roles                                    (all members)
 //   mass partials + final sums                             (per group)
-// recorded once into a hipGraph on a private stream and replayed n_long times;
-// with tracing on, the same sequence is launched directly with an event pair
-// around each launch.
+// over three state buffers whose roles (start state, two running buffers)
+// rotate from one long step to the next; the roles cycle with period 2 or 3,
+// so each long step replays one of at most three hipGraphs recorded on a
+// private stream.  With tracing on, the same sequence is launched directly
+// with an event pair around each launch.
 #include "hevi.h"
 
 #include <hip/hip_runtime.h>
@@ -42,22 +44,28 @@ struct MemberHost {
     int nx = 0, ny = 0, nz = 0, L = 0;
     double dx = 0, dy = 0, beta = 0.55, dt = -1.0;
     std::vector<double> zf;
+    std::vector<double> h;     // surface heights (terrain), empty when flat
     size_t ncell = 0;
     hv::MemberDev dev{};       // host copy of the device record
-    int roles[3] = {0, 1, 2};  // host mirror of dev.roles
     double mass_ref = 0.0;
     bool have_state = false;
 };
 
 struct GroupHost {
     int L = 0;
+    bool terrain = false;
     std::vector<int> ids;
     int *d_ids = nullptr;
-    int *d_prefix[3] = {};     // block prefix per tile shape
-    int *d_pprefix = nullptr;  // prefix of partial counts
+    unsigned *d_blk[3] = {};   // per tile shape: block -> slot << 24 | tile (nm > 1)
+    unsigned *d_pblk = nullptr;  // block -> slot << 24 | partial (nm > 1)
     int nblocks[3] = {};
     int npblocks = 0;
     int shape[NKIND] = {0, 0, 0};  // index into kShapes per kernel kind
+};
+
+struct GraphEntry {
+    int n_short, roles[3];
+    hipGraphExec_t exec;
 };
 
 }  // namespace
@@ -71,8 +79,8 @@ struct hv_ens {
     std::vector<MemberHost> m;
     std::vector<GroupHost> groups;
     hv::MemberDev *d_mem = nullptr;
-    hipGraphExec_t exec = nullptr;
-    int graph_nshort = -1;
+    int roles[3] = {0, 1, 2};        // start/current buffer, two running buffers
+    std::vector<GraphEntry> graphs;
     std::string err = "no error";
 
     struct Pending { int kind; hipEvent_t a, b; };
@@ -84,7 +92,7 @@ struct hv_ens {
 
     ~hv_ens()
     {
-        if (exec) (void)hipGraphExecDestroy(exec);
+        for (auto &g : graphs) (void)hipGraphExecDestroy(g.exec);
         for (auto &p : pending) { pool.push_back(p.a); pool.push_back(p.b); }
         for (hipEvent_t e : pool) (void)hipEventDestroy(e);
         if (fork) (void)hipEventDestroy(fork);
@@ -125,12 +133,18 @@ std::string check_desc(const hv_grid_desc *d)
     if (d->precision < HV_FP64 || d->precision > HV_MIXED) return "unknown precision";
     if (d->layout != HV_IJK && d->layout != HV_KIJ) return "unknown layout";
     if (!(d->beta >= 0.5 && d->beta <= 1.0)) return "beta must be in [0.5, 1]";
+    if (d->terrain) {
+        const double H = d->zeta_faces[d->nz];
+        const size_t nxy = (size_t)d->nx * d->ny;
+        for (size_t c = 0; c < nxy; ++c)
+            if (!std::isfinite(d->terrain[c]) || !(1.0 - d->terrain[c] / H >= 0.1))
+                return "terrain heights must be finite with 1 - h/H >= 0.1";
+    }
     return "";
 }
 
 bool unsupported(const hv_grid_desc *d, std::string *why)
 {
-    if (d->terrain) { *why = "terrain-following coordinates are not built (terrain must be NULL)"; return true; }
     if (d->div_damp != 0.0) { *why = "divergence damping is not built (div_damp must be 0)"; return true; }
     return false;
 }
@@ -147,23 +161,37 @@ struct Carve {
     }
 };
 
-// Workspace plan of an ensemble.  With base == nullptr only sizes are computed.
+// Workspace plan of an ensemble.
 struct Plan {
     size_t total = 0;
     size_t table = 0;
-    std::vector<size_t> group_off;  // per group: ids, 3 prefixes, partial prefix
-    std::vector<size_t> member_off; // per member: 25 arrays, vm, partials, sums
+    std::vector<size_t> group_off;  // per group: ids, 3 block maps, partial map
+    std::vector<size_t> member_off; // per member: 25 arrays (+4 and geometry over
+                                    // terrain), vm, partials, sums
 };
 
+size_t group_words(const std::vector<int> &ids, const hv_grid_desc *d)
+{
+    size_t w = ids.size();
+    if (ids.size() > 1) {
+        for (int s = 0; s < 3; ++s)
+            for (int q : ids) w += (size_t)hv::tiles_of(d[q].nx, d[q].ny, kShapes[s]);
+        for (int q : ids) w += (size_t)hv::partials_of(d[q].nx, d[q].ny);
+    }
+    return w;
+}
+
+// Members grouped by (flat before terrain, nz): one launch per group and phase.
 std::vector<std::vector<int>> group_members(int n, const hv_grid_desc *d)
 {
     std::vector<std::vector<int>> g;
-    for (int nz : {32, 64, 128}) {
-        std::vector<int> ids;
-        for (int q = 0; q < n; ++q)
-            if (d[q].nz == nz) ids.push_back(q);
-        if (!ids.empty()) g.push_back(ids);
-    }
+    for (int tr = 0; tr < 2; ++tr)
+        for (int nz : {32, 64, 128}) {
+            std::vector<int> ids;
+            for (int q = 0; q < n; ++q)
+                if (d[q].nz == nz && (d[q].terrain != nullptr) == (tr == 1)) ids.push_back(q);
+            if (!ids.empty()) g.push_back(ids);
+        }
     return g;
 }
 
@@ -172,15 +200,17 @@ Plan make_plan(int n, const hv_grid_desc *d)
     Plan p;
     Carve c;
     p.table = c.take(sizeof(hv::MemberDev) * (size_t)n);
-    for (auto &ids : group_members(n, d)) {
-        const size_t nm = ids.size();
-        p.group_off.push_back(c.take(sizeof(int) * (nm + 4 * (nm + 1))));
-    }
+    for (auto &ids : group_members(n, d)) p.group_off.push_back(c.take(sizeof(int) * group_words(ids, d)));
     const size_t es = elem_size(d[0].precision);
     for (int q = 0; q < n; ++q) {
         const size_t ncell = (size_t)d[q].nx * d[q].ny * d[q].nz;
         const size_t start = c.take(0);
         for (int a = 0; a < 25; ++a) c.take(ncell * es);
+        if (d[q].terrain) {
+            // Omega, three reference fields, per-column geometry
+            for (int a = 0; a < 4; ++a) c.take(ncell * es);
+            c.take(sizeof(double) * hv::GEO_NFIELDS * (size_t)d[q].nx * d[q].ny);
+        }
         c.take(sizeof(double) * hv::VM_NFIELDS * d[q].nz);
         c.take(sizeof(double) * (size_t)hv::partials_of(d[q].nx, d[q].ny));
         c.take(sizeof(double) * 4);
@@ -216,10 +246,13 @@ void from_device_order(int layout, const MemberHost &m, const T *src, double *ds
                 dst[canon(i, j, k, m.nx, m.ny)] = (double)src[dev_index(layout, m, i, j, k)];
 }
 
+// Per-level table; rho, rt, p are the reference columns (NULL over terrain,
+// where the reference is per cell).
 void fill_vmet(const MemberHost &m, const double *rho, const double *rt, const double *p,
                std::vector<double> &vm)
 {
     const int nz = m.nz;
+    const double H = m.zf[nz];
     vm.assign((size_t)hv::VM_NFIELDS * nz, 0.0);
     auto at = [&](int f, int k) -> double & { return vm[(size_t)f * nz + k]; };
     for (int k = 0; k < nz; ++k) {
@@ -228,9 +261,13 @@ void fill_vmet(const MemberHost &m, const double *rho, const double *rt, const d
         at(hv::VM_RDZ, k) = 1.0 / dz;
         at(hv::VM_VOL, k) = m.dx * m.dy * dz;
         at(hv::VM_ZC, k) = 0.5 * (m.zf[k + 1] + m.zf[k]);
-        at(hv::VM_RHO, k) = rho[k];
-        at(hv::VM_RT, k) = rt[k];
-        at(hv::VM_P, k) = p[k];
+        at(hv::VM_DC, k) = 1.0 - 0.5 * (m.zf[k] + m.zf[k + 1]) / H;
+        at(hv::VM_DF, k) = 1.0 - m.zf[k] / H;
+        if (rho) {
+            at(hv::VM_RHO, k) = rho[k];
+            at(hv::VM_RT, k) = rt[k];
+            at(hv::VM_P, k) = p[k];
+        }
         if (k == 0) {
             at(hv::VM_DZF, k) = 1.0;
             at(hv::VM_RDZF, k) = 1.0;
@@ -245,24 +282,52 @@ void fill_vmet(const MemberHost &m, const double *rho, const double *rt, const d
     }
 }
 
+// Per-column geometry of z = zeta + h (1 - zeta/H): J = 1 - h/H, the face
+// Jacobians as means of the two columns, the face slopes as differences of h.
+void fill_geo(const MemberHost &m, std::vector<double> &geo)
+{
+    const int nx = m.nx, ny = m.ny;
+    const double H = m.zf[m.nz];
+    geo.assign((size_t)hv::GEO_NFIELDS * nx * ny, 0.0);
+    auto wrap = [](int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); };
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const double h = m.h[(size_t)j * nx + i];
+            const double hw = m.h[(size_t)j * nx + wrap(i - 1, nx)];
+            const double hs = m.h[(size_t)wrap(j - 1, ny) * nx + i];
+            double *g = &geo[((size_t)j * nx + i) * hv::GEO_NFIELDS];
+            g[hv::GEO_J] = 1.0 - h / H;
+            g[hv::GEO_JU] = 0.5 * ((1.0 - hw / H) + (1.0 - h / H));
+            g[hv::GEO_JV] = 0.5 * ((1.0 - hs / H) + (1.0 - h / H));
+            g[hv::GEO_SU] = (h - hw) / m.dx;
+            g[hv::GEO_SV] = (h - hs) / m.dy;
+            g[hv::GEO_H] = h;
+        }
+}
+
 hipError_t sync(hv_ens *e) { return hipStreamSynchronize(e->stream); }
 
-hv::Group group_launch(const hv_ens *e, const GroupHost &g, int kind)
+// Launch description of group g for a kernel kind (< 0: the sums).
+hv::Group group_launch(const hv_ens *e, const GroupHost &g, int kind, int src, int dst = 0)
 {
-    hv::Group gr;
+    hv::Group gr{};
     gr.mem = e->d_mem;
     gr.ids = g.d_ids;
     gr.nm = (int)g.ids.size();
+    gr.src = src;
+    gr.dst = dst;
+    gr.terrain = g.terrain ? 1 : 0;
     if (kind < 0) {
-        gr.prefix = g.d_pprefix;
+        gr.blk = g.d_pblk;
         gr.nblocks = g.npblocks;
         gr.ti_log2 = 4;
     } else {
         const int sh = g.shape[kind];
-        gr.prefix = g.d_prefix[sh];
+        gr.blk = g.d_blk[sh];
         gr.nblocks = g.nblocks[sh];
         gr.ti_log2 = kShapes[sh];
     }
+    gr.first = g.ids[0];
     return gr;
 }
 
@@ -309,48 +374,55 @@ hipError_t fold_trace(hv_ens *e)
     return hipSuccess;
 }
 
-// Enqueue one long step of every member on stream s.
-hipError_t enqueue_long_step(hv_ens *e, int n_short, hipStream_t s)
+// Enqueue one long step of every member on stream s, for buffer roles r.
+hipError_t enqueue_long_step(hv_ens *e, int n_short, const int r[3], hipStream_t s)
 {
-    hipError_t r = hipSuccess;
+    const double frac[3] = {1.0 / 3.0, 0.5, 1.0};
+    const int P = r[0], R[2] = {r[1], r[2]};
+    hipError_t err = hipSuccess;
     for (int st = 0; st < 3; ++st) {
+        const int in = st == 0 ? P : R[(n_short - 1) & 1];
         for (auto &g : e->groups) {
-            const hv::Group gp = group_launch(e, g, KIND_PREP), gf = group_launch(e, g, KIND_FLUX);
-            r = traced(e, s, HV_K_SLOW_PREP,
-                       [&] { return hv::launch_slow_prep(e->prec, e->layout, g.L, gp, st, n_short, s); });
-            if (r != hipSuccess) return r;
-            r = traced(e, s, HV_K_SLOW_FLUX,
-                       [&] { return hv::launch_slow_flux(e->prec, e->layout, g.L, gf, st, n_short, s); });
-            if (r != hipSuccess) return r;
+            const hv::Group gp = group_launch(e, g, KIND_PREP, in), gf = group_launch(e, g, KIND_FLUX, in);
+            err = traced(e, s, HV_K_SLOW_PREP, [&] { return hv::launch_slow_prep(e->prec, e->layout, g.L, gp, s); });
+            if (err != hipSuccess) return err;
+            err = traced(e, s, HV_K_SLOW_FLUX, [&] { return hv::launch_slow_flux(e->prec, e->layout, g.L, gf, s); });
+            if (err != hipSuccess) return err;
         }
-        for (int q = 0; q < n_short; ++q)
+        for (int q = 0; q < n_short; ++q) {
+            const int src = q == 0 ? P : R[(q - 1) & 1], dst = R[q & 1];
             for (auto &g : e->groups) {
-                const hv::Group gs = group_launch(e, g, KIND_SHORT);
-                r = traced(e, s, HV_K_SHORT_STEP, [&] {
-                    return hv::launch_short_step(e->prec, e->layout, g.L, gs, st, q, n_short, s);
+                const hv::Group gs = group_launch(e, g, KIND_SHORT, src, dst);
+                err = traced(e, s, HV_K_SHORT_STEP, [&] {
+                    return hv::launch_short_step(e->prec, e->layout, g.L, gs, frac[st] / n_short, s);
                 });
-                if (r != hipSuccess) return r;
+                if (err != hipSuccess) return err;
             }
+        }
     }
-    r = hv::launch_rotate(e->d_mem, e->n, n_short, s);
-    if (r != hipSuccess) return r;
+    const int cur = R[(n_short - 1) & 1];
     for (auto &g : e->groups) {
-        const hv::Group gm = group_launch(e, g, -1);
-        r = traced(e, s, HV_K_MASS, [&] { return hv::launch_sums(e->prec, e->layout, g.L, gm, false, s); });
-        if (r != hipSuccess) return r;
+        const hv::Group gm = group_launch(e, g, -1, cur);
+        err = traced(e, s, HV_K_MASS, [&] { return hv::launch_sums(e->prec, e->layout, g.L, gm, false, s); });
+        if (err != hipSuccess) return err;
     }
     return hipSuccess;
 }
 
-void mirror_rotate(hv_ens *e, int n_short)
+// The long step's result becomes the start buffer of the next long step.
+void rotate_roles(int r[3], int n_short)
 {
-    for (auto &m : e->m) {
-        const int cur = m.roles[1 + ((n_short - 1) & 1)];
-        const int a = m.roles[0], b = m.roles[1 + (n_short & 1)];
-        m.roles[0] = cur;
-        m.roles[1] = a;
-        m.roles[2] = b;
-    }
+    const int cur = r[1 + ((n_short - 1) & 1)];
+    const int a = r[0], b = r[1 + (n_short & 1)];
+    r[0] = cur;
+    r[1] = a;
+    r[2] = b;
+}
+
+void drop_graphs(hv_ens *e)
+{
+    for (auto &g : e->graphs) (void)hipGraphExecDestroy(g.exec);
+    e->graphs.clear();
 }
 
 // ---- autotuner cache: one line per key, "key ti_prep ti_flux ti_short" ----
@@ -369,7 +441,8 @@ std::string tune_key(const hv_ens *e, const GroupHost &g)
     int b = 0;
     while ((size_t(1) << (b + 1)) <= cols) ++b;
     std::ostringstream k;
-    k << "gfx950:p" << e->prec << ":l" << e->layout << ":L" << g.L << ":c2^" << b << ":m" << g.ids.size();
+    k << "gfx950:p" << e->prec << ":l" << e->layout << ":L" << g.L << (g.terrain ? ":t" : "") << ":c2^" << b
+      << ":m" << g.ids.size();
     return k.str();
 }
 
@@ -443,12 +516,26 @@ int ens_create(hv_ens *e, int n, const hv_grid_desc *descs, void *ws, size_t byt
         hv::MemberDev &v = m.dev;
         v.nx = m.nx; v.ny = m.ny; v.nz = m.nz;
         v.npart = hv::partials_of(m.nx, m.ny);
-        v.roles[0] = 0; v.roles[1] = 1; v.roles[2] = 2; v.roles[3] = 0;
         v.rdx = 1.0 / m.dx; v.rdy = 1.0 / m.dy; v.beta = m.beta; v.dt = 0.0;
         for (int b = 0; b < 3; ++b)
             for (int f = 0; f < 5; ++f) v.st[b][f] = base + c.take(m.ncell * e->esize);
         for (int f = 0; f < 7; ++f) v.slow[f] = base + c.take(m.ncell * e->esize);
         for (int f = 0; f < 3; ++f) v.spec[f] = base + c.take(m.ncell * e->esize);
+        v.spec[3] = nullptr;
+        v.geo = nullptr;
+        v.ref[0] = v.ref[1] = v.ref[2] = nullptr;
+        if (d.terrain) {
+            m.h.assign(d.terrain, d.terrain + (size_t)d.nx * d.ny);
+            v.spec[3] = base + c.take(m.ncell * e->esize);
+            for (int f = 0; f < 3; ++f) v.ref[f] = base + c.take(m.ncell * e->esize);
+            v.geo = (const double *)(base + c.take(sizeof(double) * hv::GEO_NFIELDS * (size_t)m.nx * m.ny));
+            std::vector<double> geo;
+            fill_geo(m, geo);
+            hipError_t r = hipMemcpyAsync((void *)v.geo, geo.data(), geo.size() * sizeof(double),
+                                          hipMemcpyHostToDevice, e->stream);
+            if (r == hipSuccess) r = sync(e);
+            if (r != hipSuccess) return hip_fail(nullptr, r, "upload geometry");
+        }
         v.vm = (const double *)(base + c.take(sizeof(double) * hv::VM_NFIELDS * m.nz));
         v.partials = (double *)(base + c.take(sizeof(double) * (size_t)v.npart));
         v.sums = (double *)(base + c.take(sizeof(double) * 4));
@@ -459,30 +546,34 @@ int ens_create(hv_ens *e, int n, const hv_grid_desc *descs, void *ws, size_t byt
         GroupHost &g = e->groups[gi];
         g.ids = gm[gi];
         g.L = descs[g.ids[0]].nz / hv::kSeg;
+        g.terrain = descs[g.ids[0]].terrain != nullptr;
         const int nm = (int)g.ids.size();
+        if (n > 255) return fail(nullptr, HV_ERR_ARG, "at most 255 members");
         int *dst = (int *)(base + p.group_off[gi]);
+        std::vector<unsigned> h;
+        h.reserve(group_words(g.ids, descs));
+        for (int a = 0; a < nm; ++a) h.push_back((unsigned)g.ids[a]);
         g.d_ids = dst;
-        for (int s = 0; s < 3; ++s) g.d_prefix[s] = dst + nm + s * (nm + 1);
-        g.d_pprefix = dst + nm + 3 * (nm + 1);
-        std::vector<int> h(nm + 4 * (nm + 1), 0);
-        for (int a = 0; a < nm; ++a) h[a] = g.ids[a];
-        for (int s = 0; s < 3; ++s) {
-            int acc = 0;
+        for (int sh = 0; sh < 3; ++sh) {
+            g.nblocks[sh] = 0;
+            if (nm > 1) g.d_blk[sh] = (unsigned *)dst + h.size();
             for (int a = 0; a < nm; ++a) {
-                h[nm + s * (nm + 1) + a] = acc;
-                acc += hv::tiles_of(e->m[g.ids[a]].nx, e->m[g.ids[a]].ny, kShapes[s]);
+                const int nt = hv::tiles_of(e->m[g.ids[a]].nx, e->m[g.ids[a]].ny, kShapes[sh]);
+                if (nt >= (1 << 24)) return fail(nullptr, HV_ERR_ARG, "member too large");
+                if (nm > 1)
+                    for (int t = 0; t < nt; ++t) h.push_back(((unsigned)g.ids[a] << 24) | (unsigned)t);
+                g.nblocks[sh] += nt;
             }
-            h[nm + s * (nm + 1) + nm] = acc;
-            g.nblocks[s] = acc;
         }
-        int acc = 0;
+        g.npblocks = 0;
+        if (nm > 1) g.d_pblk = (unsigned *)dst + h.size();
         for (int a = 0; a < nm; ++a) {
-            h[nm + 3 * (nm + 1) + a] = acc;
-            acc += e->m[g.ids[a]].dev.npart;
+            const int np = e->m[g.ids[a]].dev.npart;
+            if (nm > 1)
+                for (int t = 0; t < np; ++t) h.push_back(((unsigned)g.ids[a] << 24) | (unsigned)t);
+            g.npblocks += np;
         }
-        h[nm + 3 * (nm + 1) + nm] = acc;
-        g.npblocks = acc;
-        hipError_t r = hipMemcpyAsync(dst, h.data(), h.size() * sizeof(int), hipMemcpyHostToDevice, e->stream);
+        hipError_t r = hipMemcpyAsync(dst, h.data(), h.size() * sizeof(unsigned), hipMemcpyHostToDevice, e->stream);
         if (r == hipSuccess) r = sync(e);
         if (r != hipSuccess) return hip_fail(nullptr, r, "upload group tables");
         int shape[NKIND];
@@ -511,10 +602,12 @@ int member_init(hv_ens *e, int q, const double *const fields[5], const double *r
         if (!fields[f]) return fail(e, HV_ERR_ARG, "NULL field pointer");
     MemberHost &m = e->m[q];
     const size_t nxy = (size_t)m.nx * m.ny;
-    for (int k = 0; k < m.nz; ++k)
+    const bool terrain = !m.h.empty();
+    const size_t nref = terrain ? m.ncell : (size_t)m.nz;
+    for (size_t k = 0; k < nref; ++k)
         if (!std::isfinite(rho_ref[k]) || !(rho_ref[k] > 0) || !std::isfinite(p_ref[k]) ||
             !(p_ref[k] > 0) || !std::isfinite(rhotheta_ref[k]) || !(rhotheta_ref[k] > 0))
-            return fail(e, HV_ERR_ARG, "reference columns must be finite and positive");
+            return fail(e, HV_ERR_ARG, "reference values must be finite and positive");
     for (int f = 0; f < 5; ++f) {
         const size_t cnt = (f == HV_RHOW ? nxy * (m.nz + 1) : nxy * m.nz);
         for (size_t c = 0; c < cnt; ++c)
@@ -526,32 +619,49 @@ int member_init(hv_ens *e, int q, const double *const fields[5], const double *r
     hipError_t r = sync(e);   // no step of this ensemble may still read the buffers
     if (r != hipSuccess) return hip_fail(e, r, "stream synchronize");
     std::vector<double> vm;
-    fill_vmet(m, rho_ref, rhotheta_ref, p_ref, vm);
+    if (terrain) fill_vmet(m, nullptr, nullptr, nullptr, vm);
+    else fill_vmet(m, rho_ref, rhotheta_ref, p_ref, vm);
     r = hipMemcpy((void *)m.dev.vm, vm.data(), vm.size() * sizeof(double), hipMemcpyHostToDevice);
     if (r != hipSuccess) return hip_fail(e, r, "hipMemcpy(vmet)");
     std::vector<double> bd;
     std::vector<float> bf;
     if (e->prec == HV_FP64) bd.resize(m.ncell);
     else bf.resize(m.ncell);
-    const int P = m.roles[0];
-    for (int f = 0; f < 5; ++f) {
+    const int P = e->roles[0];
+    auto upload = [&](const double *host, void *dev) -> hipError_t {
         const void *src;
-        if (e->prec == HV_FP64) { to_device_order(e->layout, m, fields[f], bd.data()); src = bd.data(); }
-        else { to_device_order(e->layout, m, fields[f], bf.data()); src = bf.data(); }
-        r = hipMemcpy(m.dev.st[P][f], src, m.ncell * e->esize, hipMemcpyHostToDevice);
-        if (r != hipSuccess) return hip_fail(e, r, "hipMemcpy(state)");
+        if (e->prec == HV_FP64) { to_device_order(e->layout, m, host, bd.data()); src = bd.data(); }
+        else { to_device_order(e->layout, m, host, bf.data()); src = bf.data(); }
+        return hipMemcpy(dev, src, m.ncell * e->esize, hipMemcpyHostToDevice);
+    };
+    for (int f = 0; f < 5; ++f)
+        if ((r = upload(fields[f], m.dev.st[P][f])) != hipSuccess) return hip_fail(e, r, "hipMemcpy(state)");
+    if (terrain) {
+        const double *refs[3] = {rho_ref, rhotheta_ref, p_ref};
+        for (int f = 0; f < 3; ++f)
+            if ((r = upload(refs[f], m.dev.ref[f])) != hipSuccess) return hip_fail(e, r, "hipMemcpy(reference)");
     }
+    // reference mass: sum of rho_ref J dx dy dzeta (J = 1 on flat ground)
     double s = 0.0, c = 0.0;
-    for (int k = 0; k < m.nz; ++k) {
-        const double x = rho_ref[k] * (m.dx * m.dy * (m.zf[k + 1] - m.zf[k])) * (double)nxy;
+    auto add = [&](double x) {
         const double t = s + x;
         c += (std::fabs(s) >= std::fabs(x)) ? ((s - t) + x) : ((x - t) + s);
         s = t;
+    };
+    const double H = m.zf[m.nz];
+    for (int k = 0; k < m.nz; ++k) {
+        const double vol = m.dx * m.dy * (m.zf[k + 1] - m.zf[k]);
+        if (!terrain) {
+            add(rho_ref[k] * vol * (double)nxy);
+            continue;
+        }
+        for (size_t col = 0; col < nxy; ++col)
+            add(rho_ref[(size_t)k * nxy + col] * vol * (1.0 - m.h[col] / H));
     }
     m.mass_ref = s + c;
     m.have_state = true;
     for (auto &g : e->groups) {
-        const hv::Group gm = group_launch(e, g, -1);
+        const hv::Group gm = group_launch(e, g, -1, e->roles[0]);
         r = hv::launch_sums(e->prec, e->layout, g.L, gm, false, e->stream);
         if (r != hipSuccess) return hip_fail(e, r, "mass after state_init");
     }
@@ -568,47 +678,57 @@ int ens_step(hv_ens *e, const double *dts, int n_long, int n_short)
     if (n_long < 0) return fail(e, HV_ERR_ARG, "n_long must be >= 0");
     if (n_short < 1) return fail(e, HV_ERR_ARG, "n_short must be >= 1");
     hipError_t r;
-    for (int q = 0; q < e->n; ++q) {
-        MemberHost &m = e->m[q];
-        if (m.dt != dts[q]) {
-            m.dt = dts[q];
-            m.dev.dt = m.dt;
-            // a kernel argument is captured at launch, so no host buffer must outlive the call
-            r = hv::launch_set_dt(e->d_mem, q, m.dt, e->stream);
-            if (r != hipSuccess) return hip_fail(e, r, "set dt");
+    bool changed = false;
+    for (int q = 0; q < e->n; ++q)
+        if (e->m[q].dt != dts[q]) {
+            e->m[q].dt = dts[q];
+            e->m[q].dev.dt = dts[q];
+            changed = true;
         }
+    if (changed) {
+        // the table is read by running steps: update it between them
+        drop_graphs(e);
+        if ((r = sync(e)) != hipSuccess) return hip_fail(e, r, "stream synchronize");
+        std::vector<hv::MemberDev> table(e->n);
+        for (int q = 0; q < e->n; ++q) table[q] = e->m[q].dev;
+        r = hipMemcpy(e->d_mem, table.data(), sizeof(hv::MemberDev) * e->n, hipMemcpyHostToDevice);
+        if (r != hipSuccess) return hip_fail(e, r, "upload member table");
     }
     if (n_long == 0) return HV_OK;
     if (e->tracing) {
         for (int s = 0; s < n_long; ++s) {
-            if ((r = enqueue_long_step(e, n_short, e->stream)) != hipSuccess) return hip_fail(e, r, "long step");
-            mirror_rotate(e, n_short);
+            if ((r = enqueue_long_step(e, n_short, e->roles, e->stream)) != hipSuccess)
+                return hip_fail(e, r, "long step");
+            rotate_roles(e->roles, n_short);
         }
         return HV_OK;
     }
-    if (!e->exec || e->graph_nshort != n_short) {
-        if (e->exec) {
-            (void)hipGraphExecDestroy(e->exec);
-            e->exec = nullptr;
-        }
-        hipGraph_t graph = nullptr;
-        if ((r = hipStreamBeginCapture(e->own, hipStreamCaptureModeThreadLocal)) != hipSuccess)
-            return hip_fail(e, r, "hipStreamBeginCapture");
-        hipError_t rl = enqueue_long_step(e, n_short, e->own);
-        r = hipStreamEndCapture(e->own, &graph);
-        if (rl != hipSuccess) { if (graph) (void)hipGraphDestroy(graph); return hip_fail(e, rl, "capture long step"); }
-        if (r != hipSuccess) return hip_fail(e, r, "hipStreamEndCapture");
-        r = hipGraphInstantiate(&e->exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (r != hipSuccess) { e->exec = nullptr; return hip_fail(e, r, "hipGraphInstantiate"); }
-        e->graph_nshort = n_short;
-    }
-    // order the private stream after the caller's work, replay, then back
+    // order the private stream after the caller's work, replay, then join back
     if ((r = hipEventRecord(e->fork, e->stream)) != hipSuccess) return hip_fail(e, r, "hipEventRecord");
     if ((r = hipStreamWaitEvent(e->own, e->fork, 0)) != hipSuccess) return hip_fail(e, r, "hipStreamWaitEvent");
     for (int s = 0; s < n_long; ++s) {
-        if ((r = hipGraphLaunch(e->exec, e->own)) != hipSuccess) return hip_fail(e, r, "hipGraphLaunch");
-        mirror_rotate(e, n_short);
+        hipGraphExec_t exec = nullptr;
+        for (auto &g : e->graphs)
+            if (g.n_short == n_short && std::equal(g.roles, g.roles + 3, e->roles)) exec = g.exec;
+        if (!exec) {
+            hipGraph_t graph = nullptr;
+            if ((r = hipStreamBeginCapture(e->own, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+                return hip_fail(e, r, "hipStreamBeginCapture");
+            const hipError_t rl = enqueue_long_step(e, n_short, e->roles, e->own);
+            r = hipStreamEndCapture(e->own, &graph);
+            if (rl != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return hip_fail(e, rl, "capture long step");
+            }
+            if (r != hipSuccess) return hip_fail(e, r, "hipStreamEndCapture");
+            r = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (r != hipSuccess) return hip_fail(e, r, "hipGraphInstantiate");
+            GraphEntry ge{n_short, {e->roles[0], e->roles[1], e->roles[2]}, exec};
+            e->graphs.push_back(ge);
+        }
+        if ((r = hipGraphLaunch(exec, e->own)) != hipSuccess) return hip_fail(e, r, "hipGraphLaunch");
+        rotate_roles(e->roles, n_short);
     }
     if ((r = hipEventRecord(e->join, e->own)) != hipSuccess) return hip_fail(e, r, "hipEventRecord");
     if ((r = hipStreamWaitEvent(e->stream, e->join, 0)) != hipSuccess) return hip_fail(e, r, "hipStreamWaitEvent");
@@ -624,7 +744,7 @@ int member_read(hv_ens *e, int q, int field, double *out)
     if (!m.have_state) return fail(e, HV_ERR_STATE, "read before state_init");
     hipError_t r = sync(e);
     if (r != hipSuccess) return hip_fail(e, r, "stream synchronize");
-    const void *src = m.dev.st[m.roles[0]][field];
+    const void *src = m.dev.st[e->roles[0]][field];
     if (e->prec == HV_FP64) {
         std::vector<double> b(m.ncell);
         if ((r = hipMemcpy(b.data(), src, m.ncell * 8, hipMemcpyDeviceToHost)) != hipSuccess)
@@ -651,7 +771,7 @@ int member_mass(hv_ens *e, int q, double *mass, double *energy)
     hipError_t r;
     if (energy)
         for (auto &g : e->groups) {
-            const hv::Group gm = group_launch(e, g, -1);
+            const hv::Group gm = group_launch(e, g, -1, e->roles[0]);
             if ((r = hv::launch_sums(e->prec, e->layout, g.L, gm, true, e->stream)) != hipSuccess)
                 return hip_fail(e, r, "energy sum");
         }
@@ -679,11 +799,12 @@ int tune(hv_ens *e, int32_t *out, int32_t *ngroups)
     if ((r = hipEventCreate(&a)) != hipSuccess) return hip_fail(e, r, "hipEventCreate");
     if ((r = hipEventCreate(&b)) != hipSuccess) { (void)hipEventDestroy(a); return hip_fail(e, r, "hipEventCreate"); }
     const int n_short = 6;
+    // stage 1 on the current state; the short step writes a running buffer
     auto launch = [&](const GroupHost &g, int kind, hipStream_t s) -> hipError_t {
-        const hv::Group gr = group_launch(e, g, kind);
-        if (kind == KIND_PREP) return hv::launch_slow_prep(e->prec, e->layout, g.L, gr, 0, n_short, s);
-        if (kind == KIND_FLUX) return hv::launch_slow_flux(e->prec, e->layout, g.L, gr, 0, n_short, s);
-        return hv::launch_short_step(e->prec, e->layout, g.L, gr, 0, 0, n_short, s);
+        const hv::Group gr = group_launch(e, g, kind, e->roles[0], e->roles[1]);
+        if (kind == KIND_PREP) return hv::launch_slow_prep(e->prec, e->layout, g.L, gr, s);
+        if (kind == KIND_FLUX) return hv::launch_slow_flux(e->prec, e->layout, g.L, gr, s);
+        return hv::launch_short_step(e->prec, e->layout, g.L, gr, 1.0 / (3.0 * n_short), s);
     };
     int rc = HV_OK;
     for (auto &g : e->groups) {
@@ -715,10 +836,7 @@ int tune(hv_ens *e, int32_t *out, int32_t *ngroups)
     (void)hipEventDestroy(b);
     e->tracing = was_tracing;
     if (rc != HV_OK) return rc;
-    if (e->exec) {
-        (void)hipGraphExecDestroy(e->exec);
-        e->exec = nullptr;
-    }
+    drop_graphs(e);
     if (ngroups) *ngroups = (int32_t)e->groups.size();
     if (out)
         for (size_t gi = 0; gi < e->groups.size(); ++gi)

@@ -116,14 +116,24 @@ def load():
     return L
 
 
-def make_desc(nx, ny, nz, dx, dy, zf, precision="fp32", layout="kij", beta=0.55):
+def make_desc(nx, ny, nz, dx, dy, zf, precision="fp32", layout="kij", beta=0.55, terrain=None):
+    """A filled hv_grid_desc plus the arrays it points into (keep them alive
+    until the grid is created).  terrain: (ny, nx) surface heights or None."""
     zf = np.ascontiguousarray(zf, dtype=np.float64)
+    keep = [zf]
+    tp = None
+    if terrain is not None:
+        t = np.ascontiguousarray(terrain, dtype=np.float64)
+        if t.shape != (int(ny), int(nx)):
+            raise ValueError(f"terrain must have shape (ny, nx) = ({ny}, {nx})")
+        keep.append(t)
+        tp = t.ctypes.data_as(_dp)
     d = GridDesc(int(nx), int(ny), int(nz), float(dx), float(dy),
-                 zf.ctypes.data_as(_dp), None,
+                 zf.ctypes.data_as(_dp), tp,
                  PRECISIONS[precision] if isinstance(precision, str) else int(precision),
                  LAYOUTS[layout] if isinstance(layout, str) else int(layout),
                  float(beta), 0.0)
-    return d, zf
+    return d, keep
 
 
 def workspace_bytes(desc: GridDesc) -> int:
@@ -137,8 +147,10 @@ def last_error(handle=None) -> str:
 class Domain:
     """One grid on the GPU: workspace, state, stepping and read-back.
 
-    ``state`` is any object with nx, ny, nz, dx, dy, zf, beta attributes (and
-    rho_ref, rt_ref, p_ref, fields when it is also used to initialise).
+    ``state`` is any object with nx, ny, nz, dx, dy, zf, beta attributes, an
+    optional ``terrain`` ((ny, nx) surface heights), and rho_ref, rt_ref,
+    p_ref, fields when it is also used to initialise (reference columns of nz
+    values on flat ground, per-cell (nz, ny, nx) arrays over terrain).
     """
 
     def __init__(self, state, precision="fp32", layout="kij", device="cuda", stream=None,
@@ -147,8 +159,9 @@ class Domain:
         self._torch = torch
         L = load()
         self.nx, self.ny, self.nz = int(state.nx), int(state.ny), int(state.nz)
-        self.desc, self._zf = make_desc(state.nx, state.ny, state.nz, state.dx, state.dy, state.zf,
-                                        precision, layout, getattr(state, "beta", 0.55))
+        self.desc, self._keep = make_desc(state.nx, state.ny, state.nz, state.dx, state.dy,
+                                          state.zf, precision, layout, getattr(state, "beta", 0.55),
+                                          getattr(state, "terrain", None))
         nbytes = workspace_bytes(self.desc)
         if nbytes == 0:
             raise HvError(HV_ERR_ARG, last_error())
@@ -245,14 +258,13 @@ class Ensemble:
         L = load()
         self.n = len(states)
         self.shapes = [(int(s.nz), int(s.ny), int(s.nx)) for s in states]
-        self._zfs = [np.ascontiguousarray(s.zf, dtype=np.float64) for s in states]
+        self._keep = []
         descs = (GridDesc * self.n)()
         for q, s in enumerate(states):
-            descs[q] = GridDesc(int(s.nx), int(s.ny), int(s.nz), float(s.dx), float(s.dy),
-                                self._zfs[q].ctypes.data_as(_dp), None,
-                                PRECISIONS[precision] if isinstance(precision, str) else int(precision),
-                                LAYOUTS[layout] if isinstance(layout, str) else int(layout),
-                                float(getattr(s, "beta", 0.55)), 0.0)
+            d, keep = make_desc(s.nx, s.ny, s.nz, s.dx, s.dy, s.zf, precision, layout,
+                                getattr(s, "beta", 0.55), getattr(s, "terrain", None))
+            descs[q] = d
+            self._keep.append(keep)
         self._descs = descs
         nbytes = int(L.hv_ens_workspace_bytes(self.n, descs))
         if nbytes == 0:

@@ -80,17 +80,39 @@ def test_create_rejects_short_or_misaligned_workspace(hv):
 
 
 def test_unbuilt_features_report_unsupported(hv):
-    d, _z = _desc(hv)
-    terr = np.zeros(16 * 12)
-    d.terrain = terr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-    h = ctypes.c_void_p()
-    rc = hv.load().hv_grid_create(ctypes.byref(d), ctypes.c_void_p(4096), 1 << 40, None,
-                                  ctypes.byref(h))
-    assert rc == hv.HV_ERR_UNSUPPORTED
     d2, _z2 = _desc(hv)
     d2.div_damp = 0.1
+    h = ctypes.c_void_p()
     assert hv.load().hv_grid_create(ctypes.byref(d2), ctypes.c_void_p(4096), 1 << 40, None,
                                     ctypes.byref(h)) == hv.HV_ERR_UNSUPPORTED
+    assert "damping" in hv.last_error()
+
+
+@pytest.mark.parametrize("bad", [float("nan"), 18500.0, 25000.0])
+def test_invalid_terrain_is_rejected_before_any_device_call(hv, bad):
+    """Heights must be finite with 1 - h/H >= 0.1 (H = 20 km here); the
+    description check runs before any HIP call."""
+    d, _z = _desc(hv)
+    terr = np.zeros(16 * 12)
+    terr[5] = bad
+    d.terrain = terr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert hv.load().hv_workspace_bytes(ctypes.byref(d)) == 0
+    assert "terrain" in hv.last_error()
+    h = ctypes.c_void_p()
+    assert hv.load().hv_grid_create(ctypes.byref(d), ctypes.c_void_p(4096), 1 << 40, None,
+                                    ctypes.byref(h)) == hv.HV_ERR_ARG
+
+
+def test_terrain_adds_its_arrays_to_the_workspace(hv):
+    d, _z = _desc(hv)
+    flat = hv.load().hv_workspace_bytes(ctypes.byref(d))
+    terr = np.full(16 * 12, 500.0)
+    d.terrain = terr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    with_t = hv.load().hv_workspace_bytes(ctypes.byref(d))
+    ncell = 16 * 12 * d.nz
+    es = 8 if d.precision == hv.PRECISIONS["fp64"] else 4
+    # Omega and three reference fields per cell, 8 float64 per column
+    assert with_t - flat >= 4 * ncell * es + 8 * 8 * 16 * 12
 
 
 def test_null_handle_calls_fail_cleanly(hv):

@@ -1,0 +1,111 @@
+"""GPU parity at the benchmark sizes, on sampled columns.
+
+One long step only reaches a bounded distance sideways: the slow sweep of a
+stage reads 3 columns away (Koren stencil of the specific velocities, which
+read the density one column over) and each short step 1 column away, and
+every stage starts from the state at the start of the long step, so stage s
+depends on columns within s (3 + n) of the output.  For n = 6 that is 27
+columns.  The oracle therefore runs on a 72 x 72 periodic patch cut from the
+full initial state around each sample; the centre 8 x 8 columns of the patch
+are then exactly the full-domain values and are compared with the GPU run of
+the whole domain, in the launch configuration the benchmark times.
+
+Samples: the domain corner (periodic wrap on both axes), the strongest
+bubble, and over terrain the highest point of the orography.
+"""
+import numpy as np
+import pytest
+
+from paper_1710_08616_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+PATCH = 72
+CORE = 4          # compare columns centre - CORE .. centre + CORE - 1
+
+
+@pytest.fixture(scope="module")
+def hv():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1710_08616_amd import hevi
+    hevi.load()
+    return hevi
+
+
+def _patch(s, ic, jc, n=PATCH):
+    ii = (np.arange(n) - n // 2 + ic) % s.nx
+    jj = (np.arange(n) - n // 2 + jc) % s.ny
+
+    def cut(f):
+        return np.ascontiguousarray(f[:, jj][:, :, ii])
+
+    refs = [cut(r) if np.ndim(r) == 3 else r for r in (s.rho_ref, s.rt_ref, s.p_ref)]
+    terrain = None if s.terrain is None else np.ascontiguousarray(s.terrain[np.ix_(jj, ii)])
+    return inputs.State(n, n, s.nz, s.dx, s.dy, s.zf, refs[0], refs[1], refs[2],
+                        [cut(f) for f in s.fields], dt=s.dt, n_short=s.n_short, n_long=1,
+                        beta=s.beta, terrain=terrain)
+
+
+def _core(f, ic, jc, nx, ny):
+    ii = (np.arange(2 * CORE) - CORE + ic) % nx
+    jj = (np.arange(2 * CORE) - CORE + jc) % ny
+    return f[:, jj][:, :, ii]
+
+
+def _samples(s):
+    pts = [(0, 0)]
+    # strongest density deficit near 5 km: a bubble
+    k = int(np.searchsorted(inputs.centres(s.zf), 5000.0))
+    j, i = np.unravel_index(int(np.argmin(s.fields[0][k])), (s.ny, s.nx))
+    pts.append((int(i), int(j)))
+    if s.terrain is not None:
+        j, i = np.unravel_index(int(np.argmax(s.terrain)), (s.ny, s.nx))
+        pts.append((int(i), int(j)))
+    return pts
+
+
+def _check(hv, oracle, s, prec):
+    print(f"case: full {s.name} {s.nx}x{s.ny}x{s.nz} {prec}: gpu step", flush=True)
+    d = hv.Domain(s, precision=prec, layout="kij")
+    d.step(s.dt, 1, s.n_short)
+    got = d.read_all()
+    m = d.mass()
+    d.close()
+    assert np.isfinite(m)
+    for (ic, jc) in _samples(s):
+        print(f"case: full {s.name} {prec}: sample ({ic}, {jc})", flush=True)
+        p = _patch(s, ic, jc)
+        ref = oracle.step(p, n_long=1)
+        twin = oracle.step(p.as_f32(), n_long=1, f32_storage=True) if prec != "fp64" else None
+        c = PATCH // 2
+        for f, name in enumerate(inputs.FIELD_NAMES):
+            a = _core(got[f], ic, jc, s.nx, s.ny)
+            b = ref[f][:, c - CORE:c + CORE, c - CORE:c + CORE]
+            scale = np.ptp(ref[f]) or 1.0
+            err = np.abs(a - b).max() / scale
+            if prec == "fp64":
+                tol = 1e-11
+            else:
+                tol = 10.0 * np.abs(twin[f] - ref[f]).max() / scale
+            assert err <= tol, (name, (ic, jc), err, tol)
+
+
+@pytest.fixture(scope="module")
+def large():
+    return inputs.workload("large")
+
+
+@pytest.fixture(scope="module")
+def terrain():
+    return inputs.workload("terrain")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_large_workload_sampled_columns_match_oracle(hv, oracle, large, prec):
+    _check(hv, oracle, large, prec)
+
+
+@pytest.mark.parametrize("prec", ["mixed"])
+def test_terrain_workload_sampled_columns_match_oracle(hv, oracle, terrain, prec):
+    _check(hv, oracle, terrain, prec)

@@ -28,6 +28,13 @@
  *    then a beta-off-centred trapezoidal vertical coupling of W, rho', Theta'
  *    that is one tridiagonal system per column, solved by the Thomas
  *    algorithm (no pivoting; the system is diagonally dominant).
+ *  - Short-step integrator, optional second form: the paper calls the short
+ *    steps a second-order Runge-Kutta scheme.  With Phi(X_b, X_e, d) the
+ *    short step above whose increments are added to X_b while every explicit
+ *    term and the (1 - beta) old-time part of the vertical coupling are taken
+ *    from X_e, the two-stage form is X* = Phi(X, X, dtau/2) and
+ *    X+ = Phi(X, X*, dtau) (midpoint rule; the forward-backward step is
+ *    Phi(X, X, dtau)).  Two column solves per short step.
  *  - RK3 stage lengths dt/3, dt/2, dt; each stage restarts its n short steps
  *    from the state at the start of the long step, with the slow tendencies
  *    evaluated on the previous stage's result.
@@ -87,6 +94,8 @@ typedef struct {
     const double *rt_ref;     /* reference rho*theta, same shape              */
     const double *p_ref;      /* reference pressure, same shape               */
     const double *terrain;    /* nx*ny surface heights, NULL = flat           */
+    int32_t short_rk2;        /* 0: forward-backward short step; 1: the
+                                 two-stage Runge-Kutta short step           */
 } or_grid;
 
 /* index of the reference value of cell c (level k) */
@@ -521,13 +530,14 @@ int or_thomas(int n, const double *a, const double *b, const double *c, const do
  * Inputs per cell m = 0..nz-1: rt (rho' after the horizontal divergence),
  * tt (Theta' after it), rp and pp (rho' and p' at the start of the short
  * step), P0, Cs, ths (stage coefficients); per level face k = 0..nz: W (old),
- * SW and E (the terrain-slope part of the flux through the zeta surface,
- * zero on flat ground).  dz and dzf are the column's own thicknesses
+ * Wb (the W the increment is added to; W itself except in the second stage
+ * of the Runge-Kutta short step), SW and E (the terrain-slope part of the
+ * flux through the zeta surface, zero on flat ground).  dz and dzf are the column's own thicknesses
  * (J dzeta with terrain).  With Omega* = beta W+ + (1-beta) W - E:
  *   rho'+_m   = rt_m - (dtau/dz_m) (Omega*_{m+1} - Omega*_m)
  *   Theta'+_m = tt_m - (dtau/dz_m) (thf_{m+1} Omega*_{m+1} - thf_m Omega*_m)
  *   p'+       = P0 + Cs Theta'+
- *   W+_k      = W_k + dtau [ SW_k - (p*_k - p*_{k-1})/dzf_k
+ *   W+_k      = Wb_k + dtau [ SW_k - (p*_k - p*_{k-1})/dzf_k
  *                            - g (a_k rho*_k + b_k rho*_{k-1}) ]
  * with p* = beta p'+ + (1-beta) p', rho* = beta rho'+ + (1-beta) rho',
  * thf the linear interpolation of ths to the faces, and W+ = Omega* = 0 on
@@ -551,8 +561,8 @@ static void col_thf(const or_col *c, const double *ths, double *thf)
 /* A, B, C, D indexed by face k (entries 1..nz-1 used). */
 static void col_assemble(const or_col *c, const double *rt, const double *tt, const double *rp,
                          const double *pp, const double *P0, const double *Cs, const double *ths,
-                         const double *W, const double *SW, double *A, double *B, double *Cc,
-                         double *D, double *thf, double *pE, double *rEs)
+                         const double *W, const double *Wb, const double *SW, double *A,
+                         double *B, double *Cc, double *D, double *thf, double *pE, double *rEs)
 {
     const int nz = c->nz;
     const double be = c->beta, dt = c->dtau, g = c->grav;
@@ -574,7 +584,7 @@ static void col_assemble(const or_col *c, const double *rt, const double *tt, co
         Cc[k] = -mu * Cs[k] * thf[k + 1] / (dzf * dzp) - mu * g * c->a[k] / dzp;
         B[k] = 1.0 + mu * thf[k] * (Cs[k] / dzp + Cs[k - 1] / dzm) / dzf
                + mu * g * (c->a[k] / dzp - c->b[k] / dzm);
-        D[k] = W[k] + dt * SW[k] - (dt / dzf) * (pE[k] - pE[k - 1])
+        D[k] = Wb[k] + dt * SW[k] - (dt / dzf) * (pE[k] - pE[k - 1])
                - dt * g * (c->a[k] * rEs[k] + c->b[k] * rEs[k - 1]);
     }
 }
@@ -598,8 +608,8 @@ static void col_update(const or_col *c, const double *rt, const double *tt, cons
  * evaluated directly from the update equations for a trial W+ (lids 0). */
 static void col_residual(const or_col *c, const double *rt, const double *tt, const double *rp,
                          const double *pp, const double *P0, const double *Cs, const double *ths,
-                         const double *W, const double *SW, const double *Wp, double *R,
-                         double *thf, double *rpo, double *tpo)
+                         const double *W, const double *Wb, const double *SW, const double *Wp,
+                         double *R, double *thf, double *rpo, double *tpo)
 {
     const int nz = c->nz;
     const double be = c->beta, dt = c->dtau, g = c->grav;
@@ -612,7 +622,7 @@ static void col_residual(const or_col *c, const double *rt, const double *tt, co
         double pkm = be * (P0[k - 1] + Cs[k - 1] * tpo[k - 1]) + (1.0 - be) * pp[k - 1];
         double rk = be * rpo[k] + (1.0 - be) * rp[k];
         double rkm = be * rpo[k - 1] + (1.0 - be) * rp[k - 1];
-        double rhs = W[k] + dt * (SW[k] - (pk - pkm) / c->dzf[k] - g * (c->a[k] * rk + c->b[k] * rkm));
+        double rhs = Wb[k] + dt * (SW[k] - (pk - pkm) / c->dzf[k] - g * (c->a[k] * rk + c->b[k] * rkm));
         R[k] = Wp[k] - rhs;
     }
 }
@@ -653,7 +663,7 @@ int or_vi_assemble(int nz, const double *zf, double beta, double dtau, double gr
     or_col c;
     double *tmp = col_setup(nz, &vm, jac, E, &c, beta, dtau, grav);
     if (!tmp) { vmet_free(&vm); return OR_ENOMEM; }
-    col_assemble(&c, rt, tt, rp, pp, P0, Cs, ths, W, SW, A, B, C, D, tmp, tmp + nz + 1,
+    col_assemble(&c, rt, tt, rp, pp, P0, Cs, ths, W, W, SW, A, B, C, D, tmp, tmp + nz + 1,
                  tmp + 2 * (nz + 1));
     A[0] = B[0] = C[0] = D[0] = 0.0;
     A[nz] = B[nz] = C[nz] = D[nz] = 0.0;
@@ -675,23 +685,27 @@ int or_vi_residual(int nz, const double *zf, double beta, double dtau, double gr
     or_col c;
     double *tmp = col_setup(nz, &vm, jac, E, &c, beta, dtau, grav);
     if (!tmp) { vmet_free(&vm); return OR_ENOMEM; }
-    col_residual(&c, rt, tt, rp, pp, P0, Cs, ths, W, SW, Wp, R, tmp, tmp + nz + 1, tmp + 2 * (nz + 1));
+    col_residual(&c, rt, tt, rp, pp, P0, Cs, ths, W, W, SW, Wp, R, tmp, tmp + nz + 1, tmp + 2 * (nz + 1));
     free(tmp);
     vmet_free(&vm);
     return OR_OK;
 }
 
 /* ------------------------------------------------------------------------
- * One short step from st_in to st_out (distinct buffers) with the stage's
- * slow arrays sl = {S_U, S_V, S_W, R_Theta, theta_s, P0_s, C_s}.
+ * One short step Phi(base, ev, dtau) into out (distinct from both) with the
+ * stage's slow arrays sl = {S_U, S_V, S_W, R_Theta, theta_s, P0_s, C_s}:
+ * increments are added to `base`; p' of the horizontal pressure gradient and
+ * the old-time (1 - beta) parts of the vertical coupling come from `ev`.
+ * The forward-backward short step is Phi(X, X, dtau).
  * ---------------------------------------------------------------------- */
 static int short_step(const or_grid *g, const or_vmet *vm, const or_geo *geo,
-                      const double *const sl[7], const double *const in[5], double dtau,
-                      double *const out[5], double *pp)
+                      const double *const sl[7], const double *const base[5],
+                      const double *const ev[5], double dtau, double *const out[5], double *pp)
 {
     const int nx = g->nx, ny = g->ny, nz = g->nz;
     const size_t nxy = (size_t)nx * ny;
-    const double *rp = in[0], *U = in[1], *V = in[2], *W = in[3], *tp = in[4];
+    const double *rp = base[0], *U = base[1], *V = base[2], *Wb = base[3], *tp = base[4];
+    const double *rpe = ev[0], *W = ev[3], *tpe = ev[4];
     const double *SU = sl[0], *SV = sl[1], *SW = sl[2], *RT = sl[3];
     const double *ths = sl[4], *P0 = sl[5], *Cs = sl[6];
     double *rpo = out[0], *Uo = out[1], *Vo = out[2], *Wo = out[3], *tpo = out[4];
@@ -699,13 +713,13 @@ static int short_step(const or_grid *g, const or_vmet *vm, const or_geo *geo,
     int bad = 0;
 #define C2(i, j) ((size_t)(j) * (size_t)nx + (size_t)(i))
 
-    /* p' of the current Theta' with the stage linearisation */
+    /* p' of the evaluation state's Theta' with the stage linearisation */
 #pragma omp parallel for schedule(static)
     for (int jk = 0; jk < ny * nz; ++jk) {
         int j = jk % ny, k = jk / ny;
         for (int i = 0; i < nx; ++i) {
             size_t c = C3(i, j, k);
-            pp[c] = P0[c] + Cs[c] * tp[c];
+            pp[c] = P0[c] + Cs[c] * tpe[c];
         }
     }
     /* horizontally explicit momentum, forward in time.  Over terrain the
@@ -766,7 +780,7 @@ static int short_step(const or_grid *g, const or_vmet *vm, const or_geo *geo,
 #pragma omp parallel reduction(| : bad)
     {
         size_t nzp = (size_t)nz + 1;
-        double *buf = (double *)malloc(sizeof(double) * nzp * 27);
+        double *buf = (double *)malloc(sizeof(double) * nzp * 28);
         if (!buf) {
             bad |= 2;
         } else {
@@ -778,6 +792,7 @@ static int short_step(const or_grid *g, const or_vmet *vm, const or_geo *geo,
             double *Wp = buf + 16 * nzp, *x = buf + 17 * nzp, *work = buf + 18 * nzp;
             double *orp = buf + 20 * nzp, *otp = buf + 21 * nzp;
             double *cdz = buf + 22 * nzp, *cdzf = buf + 23 * nzp, *cE = buf + 24 * nzp;
+            double *cWb = buf + 27 * nzp;
 #pragma omp for schedule(static)
             for (long col_id = 0; col_id < (long)nxy; ++col_id) {
                 int i = (int)(col_id % nx), j = (int)(col_id / nx);
@@ -786,12 +801,13 @@ static int short_step(const or_grid *g, const or_vmet *vm, const or_geo *geo,
                 const double sv0 = geo->sv[C2(i, j)], sv1 = geo->sv[C2(i, wrapi(j + 1, ny))];
                 for (int m = 0; m < nz; ++m) {
                     size_t c = C3(i, j, m);
-                    crt[m] = rpo[c]; ctt[m] = tpo[c]; crp[m] = rp[c]; cpp[m] = pp[c];
+                    crt[m] = rpo[c]; ctt[m] = tpo[c]; crp[m] = rpe[c]; cpp[m] = pp[c];
                     cP0[m] = P0[c]; cCs[m] = Cs[c]; cth[m] = ths[c];
                     cdz[m] = jc * vm->dz[m];
                 }
                 for (int k = 0; k <= nz; ++k) {
                     cW[k] = W[C3(i, j, k)];
+                    cWb[k] = Wb[C3(i, j, k)];
                     cSW[k] = SW[C3(i, j, k)];
                     cdzf[k] = jc * vm->dzf[k];
                     cE[k] = 0.0;
@@ -805,7 +821,8 @@ static int short_step(const or_grid *g, const or_vmet *vm, const or_geo *geo,
                     }
                 }
                 or_col col = {nz, cdz, cdzf, vm->a, vm->b, cE, g->beta, dtau, g->grav};
-                col_assemble(&col, crt, ctt, crp, cpp, cP0, cCs, cth, cW, cSW, A, B, Cc, D, thf, pE, rEs);
+                col_assemble(&col, crt, ctt, crp, cpp, cP0, cCs, cth, cW, cWb, cSW, A, B, Cc, D, thf, pE,
+                             rEs);
                 Wp[0] = 0.0;
                 Wp[nz] = 0.0;
                 if (nz > 1) {
@@ -842,7 +859,8 @@ static void round_f32(double *x, size_t n)
  * Stage s = 1, 2, 3 has length dt/3, dt/2, dt: the slow sweep is evaluated on
  * the previous stage's result (the start state for s = 1), then the n short
  * steps of length (stage length)/n restart from the start state.  The third
- * stage's result is the new state.
+ * stage's result is the new state.  Each short step is the forward-backward
+ * step, or with g->short_rk2 the two-stage Runge-Kutta form.
  *
  * f32_storage != 0 rounds every stored field and slow array to binary32
  * after each sweep: a model of binary32 storage used to size the tolerances
@@ -861,11 +879,11 @@ int or_step(const or_grid *g, double *const st[5], double dt, int n_long, int n_
         vmet_free(&vm); geo_free(&geo);
         return OR_ENOMEM;
     }
-    double *mem = (double *)malloc(sizeof(double) * (3 * (4 * n + nw) + 6 * n + nw + n));
+    double *mem = (double *)malloc(sizeof(double) * (4 * (4 * n + nw) + 6 * n + nw + n));
     if (!mem) { vmet_free(&vm); geo_free(&geo); return OR_ENOMEM; }
-    double *bufs[3][5], *sl[7], *pp;
+    double *bufs[4][5], *sl[7], *pp;   /* [3]: first-stage value of the RK2 short step */
     double *p = mem;
-    for (int b = 0; b < 3; ++b)
+    for (int b = 0; b < 4; ++b)
         for (int f = 0; f < 5; ++f) { bufs[b][f] = p; p += sz[f]; }
     for (int f = 0; f < 7; ++f) { sl[f] = p; p += (f == 2 ? nw : n); }
     pp = p;
@@ -887,8 +905,20 @@ int or_step(const or_grid *g, double *const st[5], double dt, int n_long, int n_
             double *const *src = start;
             for (int q = 0; q < n_short; ++q) {
                 double *const *dst = bufs[1 + (q & 1)];
-                int r = short_step(g, &vm, &geo, (const double *const *)sl,
-                                   (const double *const *)src, dtau, dst, pp);
+                const double *const *cs = (const double *const *)sl;
+                const double *const *in = (const double *const *)src;
+                int r;
+                if (g->short_rk2) {
+                    /* X* = Phi(X, X, dtau/2), then X+ = Phi(X, X*, dtau) */
+                    r = short_step(g, &vm, &geo, cs, in, in, 0.5 * dtau, bufs[3], pp);
+                    if (r == OR_ENOMEM) { rc = r; break; }
+                    if (r == OR_ENOTDOM) rc = r;
+                    if (f32_storage)
+                        for (int f = 0; f < 5; ++f) round_f32(bufs[3][f], sz[f]);
+                    r = short_step(g, &vm, &geo, cs, in, (const double *const *)bufs[3], dtau, dst, pp);
+                } else {
+                    r = short_step(g, &vm, &geo, cs, in, in, dtau, dst, pp);
+                }
                 if (r == OR_ENOMEM) { rc = r; break; }
                 if (r == OR_ENOTDOM) rc = r;
                 if (f32_storage)
@@ -919,7 +949,7 @@ int or_short_step(const or_grid *g, const double *const sl[7], const double *con
     }
     double *pp = (double *)malloc(n * sizeof(double));
     if (!pp) { vmet_free(&vm); geo_free(&geo); return OR_ENOMEM; }
-    int rc = short_step(g, &vm, &geo, sl, in, dtau, out, pp);
+    int rc = short_step(g, &vm, &geo, sl, in, in, dtau, out, pp);
     free(pp);
     vmet_free(&vm);
     geo_free(&geo);

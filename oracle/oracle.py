@@ -46,7 +46,7 @@ class _Grid(ctypes.Structure):
                 ("donor_cell", ctypes.c_int32), ("dx", ctypes.c_double), ("dy", ctypes.c_double),
                 ("beta", ctypes.c_double), ("grav", ctypes.c_double),
                 ("zf", _dp), ("rho_ref", _dp), ("rt_ref", _dp), ("p_ref", _dp),
-                ("terrain", _dp)]
+                ("terrain", _dp), ("short_rk2", ctypes.c_int32)]
 
 
 def lib():
@@ -93,7 +93,8 @@ def _f64(a) -> np.ndarray:
 class _GridHolder:
     """A filled or_grid plus the arrays it points into (kept alive)."""
 
-    def __init__(self, s, grav: float = GRAV, beta=None, donor_cell: bool = False):
+    def __init__(self, s, grav: float = GRAV, beta=None, donor_cell: bool = False,
+                 short_rk2: bool = False):
         self.zf = _f64(s.zf)
         self.rho_ref = _f64(s.rho_ref)
         self.rt_ref = _f64(s.rt_ref)
@@ -111,7 +112,8 @@ class _GridHolder:
                        float(s.dx), float(s.dy),
                        float(s.beta if beta is None else beta), float(grav),
                        _ptr(self.zf), _ptr(self.rho_ref), _ptr(self.rt_ref), _ptr(self.p_ref),
-                       _dp() if self.terrain is None else _ptr(self.terrain))
+                       _dp() if self.terrain is None else _ptr(self.terrain),
+                       1 if short_rk2 else 0)
 
     @property
     def ref(self):
@@ -129,16 +131,18 @@ def _shapes(s):
 
 
 def step(s, dt=None, n_long=None, n_short=None, f32_storage=False, grav: float = GRAV,
-         check=True, donor_cell: bool = False) -> List[np.ndarray]:
+         check=True, donor_cell: bool = False, short_rk2: bool = False) -> List[np.ndarray]:
     """Advance a copy of the state's fields; returns the new five fields.
 
     donor_cell=True swaps the Koren face values for first-order upwind ones, a
     linear operator that exposes the RK3 stage structure in closed form (tests
-    only; the model itself always uses the Koren limiter)."""
+    only; the model itself always uses the Koren limiter).  short_rk2=True
+    takes the two-stage Runge-Kutta short step instead of the
+    forward-backward one."""
     dt = s.dt if dt is None else dt
     n_long = s.n_long if n_long is None else n_long
     n_short = s.n_short if n_short is None else n_short
-    gh = _GridHolder(s, grav, donor_cell=donor_cell)
+    gh = _GridHolder(s, grav, donor_cell=donor_cell, short_rk2=short_rk2)
     f = [_f64(x).copy() for x in s.fields]
     rc = lib().or_step(gh.ref, _ptr_array(f), float(dt), int(n_long), int(n_short),
                        1 if f32_storage else 0)

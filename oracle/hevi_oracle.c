@@ -35,6 +35,14 @@
  *    from X_e, the two-stage form is X* = Phi(X, X, dtau/2) and
  *    X+ = Phi(X, X*, dtau) (midpoint rule; the forward-backward step is
  *    Phi(X, X, dtau)).  Two column solves per short step.
+ *  - Lateral and upper damping (optional), the kernel of the paper's
+ *    Listing 1: the target of each prognostic is the boundary state
+ *    interpolated in time, mtratio (ref + bnd1) + tratio (ref + bnd2) - ref
+ *    (ref = 0 for the momenta), tratio = (t - t1)/(t2 - t1) clipped to
+ *    [0, 1], mtratio = 1 - tratio; after every short step each value
+ *    relaxes implicitly, X <- (X + c X_target) / (1 + c), c = dtau (nu_lat of
+ *    its column + nu_top of its level), with t the time at the end of that
+ *    short step.  Values with nu = 0, and W on the lids, are left untouched.
  *  - RK3 stage lengths dt/3, dt/2, dt; each stage restarts its n short steps
  *    from the state at the start of the long step, with the slow tendencies
  *    evaluated on the previous stage's result.
@@ -96,6 +104,13 @@ typedef struct {
     const double *terrain;    /* nx*ny surface heights, NULL = flat           */
     int32_t short_rk2;        /* 0: forward-backward short step; 1: the
                                  two-stage Runge-Kutta short step           */
+    /* lateral and upper damping after every short step (nu_lat NULL: off) */
+    const double *nu_lat;     /* nx*ny lateral rate (1/s) per column         */
+    const double *nu_top;     /* nz    upper rate (1/s) per level            */
+    const double *bnd1[5];    /* boundary states at times t1 and t2, in the  */
+    const double *bnd2[5];    /* layout of the prognostic fields             */
+    double t1, t2;            /* times of bnd1 and bnd2, t2 > t1             */
+    double time0;             /* model time at the start of or_step          */
 } or_grid;
 
 /* index of the reference value of cell c (level k) */
@@ -853,6 +868,43 @@ static void round_f32(double *x, size_t n)
 }
 
 /* ------------------------------------------------------------------------
+ * Lateral and upper damping of st in place at time t after a short step of
+ * length dtau (see the header).  W's level face k uses nu_top of level k.
+ * ---------------------------------------------------------------------- */
+int or_damp(const or_grid *g, double *const st[5], double dtau, double t)
+{
+    if (!g || !g->nu_lat || !g->nu_top) return OR_OK;
+    const int nx = g->nx, ny = g->ny, nz = g->nz;
+    const size_t nxy = (size_t)nx * ny;
+    double tr = (t - g->t1) / (g->t2 - g->t1);
+    tr = tr < 0.0 ? 0.0 : (tr > 1.0 ? 1.0 : tr);
+    const double mt = 1.0 - tr;
+    for (int f = 0; f < 5; ++f) {
+        const int nk = f == 3 ? nz + 1 : nz;
+        double *x = st[f];
+        const double *b1 = g->bnd1[f], *b2 = g->bnd2[f];
+#pragma omp parallel for schedule(static)
+        for (int jk = 0; jk < ny * nk; ++jk) {
+            int j = jk % ny, k = jk / ny;
+            if (f == 3 && (k == 0 || k == nz)) continue;
+            const int kl = k < nz ? k : nz - 1;
+            for (int i = 0; i < nx; ++i) {
+                size_t c = C3(i, j, k);
+                const double nu = g->nu_lat[(size_t)j * nx + i] + g->nu_top[kl];
+                if (nu == 0.0) continue;
+                double ref = 0.0;
+                if (f == 0) ref = g->rho_ref[RI(g, c, k)];
+                if (f == 4) ref = g->rt_ref[RI(g, c, k)];
+                const double tgt = mt * (ref + b1[c]) + tr * (ref + b2[c]) - ref;
+                const double cf = dtau * nu;
+                x[c] = (x[c] + cf * tgt) / (1.0 + cf);
+            }
+        }
+    }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------
  * n_long RK3 long steps of length dt with n_short short steps per stage,
  * in place on st = {rho', U, V, W, Theta'}.
  *
@@ -921,6 +973,8 @@ int or_step(const or_grid *g, double *const st[5], double dt, int n_long, int n_
                 }
                 if (r == OR_ENOMEM) { rc = r; break; }
                 if (r == OR_ENOTDOM) rc = r;
+                /* damping at the end of the short step: t_n + (q+1) dtau */
+                or_damp(g, dst, dtau, g->time0 + step * dt + (q + 1) * dtau);
                 if (f32_storage)
                     for (int f = 0; f < 5; ++f) round_f32(dst[f], sz[f]);
                 src = dst;
@@ -1030,4 +1084,35 @@ int or_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* ------------------------------------------------------------------------
+ * Seven-point diffusion, the stencil that dominates the paper's reduced
+ * weather application (Sect. 4, performance model of no-cache and
+ * perfect-cache bandwidth).  One explicit step on a uniform grid:
+ *   q+ = q + ((kx lx + ky ly) + kz lz),  l_d = (q_{-d} + q_{+d}) - 2 q,
+ * kd = nu dt / d^2, periodic in x and y, zero flux through the lids (the
+ * missing vertical neighbour is the cell itself).  q and out are nz*ny*nx,
+ * i fastest; out must not alias q.
+ * ---------------------------------------------------------------------- */
+int or_diffuse(int nx, int ny, int nz, double kx, double ky, double kz, const double *q,
+               double *out)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || !q || !out) return OR_EARG;
+    const size_t nxy = (size_t)nx * ny;
+#pragma omp parallel for schedule(static)
+    for (int jk = 0; jk < ny * nz; ++jk) {
+        int j = jk % ny, k = jk / ny;
+        for (int i = 0; i < nx; ++i) {
+            size_t c = C3(i, j, k);
+            double qc = q[c];
+            double lx = (q[C3(wrapi(i - 1, nx), j, k)] + q[C3(wrapi(i + 1, nx), j, k)]) - 2.0 * qc;
+            double ly = (q[C3(i, wrapi(j - 1, ny), k)] + q[C3(i, wrapi(j + 1, ny), k)]) - 2.0 * qc;
+            double qd = k > 0 ? q[C3(i, j, k - 1)] : qc;
+            double qu = k < nz - 1 ? q[C3(i, j, k + 1)] : qc;
+            double lz = (qd + qu) - 2.0 * qc;
+            out[c] = qc + ((kx * lx + ky * ly) + kz * lz);
+        }
+    }
+    return OR_OK;
 }

@@ -46,7 +46,9 @@ class _Grid(ctypes.Structure):
                 ("donor_cell", ctypes.c_int32), ("dx", ctypes.c_double), ("dy", ctypes.c_double),
                 ("beta", ctypes.c_double), ("grav", ctypes.c_double),
                 ("zf", _dp), ("rho_ref", _dp), ("rt_ref", _dp), ("p_ref", _dp),
-                ("terrain", _dp), ("short_rk2", ctypes.c_int32)]
+                ("terrain", _dp), ("short_rk2", ctypes.c_int32),
+                ("nu_lat", _dp), ("nu_top", _dp), ("bnd1", _dp * 5), ("bnd2", _dp * 5),
+                ("t1", ctypes.c_double), ("t2", ctypes.c_double), ("time0", ctypes.c_double)]
 
 
 def lib():
@@ -75,6 +77,8 @@ def lib():
         L.or_mass.argtypes = [ctypes.c_void_p, _dp]
         L.or_energy.restype = ctypes.c_double
         L.or_energy.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.or_diffuse.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + [_dp, _dp]
+        L.or_damp.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double]
         L.or_threads.restype = ctypes.c_int
         L.or_threads.argtypes = []
         _lib = L
@@ -94,7 +98,7 @@ class _GridHolder:
     """A filled or_grid plus the arrays it points into (kept alive)."""
 
     def __init__(self, s, grav: float = GRAV, beta=None, donor_cell: bool = False,
-                 short_rk2: bool = False):
+                 short_rk2: bool = False, time0: float = 0.0):
         self.zf = _f64(s.zf)
         self.rho_ref = _f64(s.rho_ref)
         self.rt_ref = _f64(s.rt_ref)
@@ -114,6 +118,22 @@ class _GridHolder:
                        _ptr(self.zf), _ptr(self.rho_ref), _ptr(self.rt_ref), _ptr(self.p_ref),
                        _dp() if self.terrain is None else _ptr(self.terrain),
                        1 if short_rk2 else 0)
+        self.g.time0 = float(time0)
+        dmp = getattr(s, "damping", None)
+        if dmp is not None:
+            self.nu_lat = _f64(dmp["nu_lat"])
+            self.nu_top = _f64(dmp["nu_top"])
+            assert self.nu_lat.shape == (s.ny, s.nx) and self.nu_top.shape == (s.nz,)
+            self.bnd = [[_f64(x) for x in dmp["bnd1"]], [_f64(x) for x in dmp["bnd2"]]]
+            for b in self.bnd:
+                assert [x.shape for x in b] == [f.shape for f in s.fields]
+            self.g.nu_lat = _ptr(self.nu_lat)
+            self.g.nu_top = _ptr(self.nu_top)
+            for f in range(5):
+                self.g.bnd1[f] = _ptr(self.bnd[0][f])
+                self.g.bnd2[f] = _ptr(self.bnd[1][f])
+            self.g.t1 = float(dmp["t1"])
+            self.g.t2 = float(dmp["t2"])
 
     @property
     def ref(self):
@@ -131,18 +151,21 @@ def _shapes(s):
 
 
 def step(s, dt=None, n_long=None, n_short=None, f32_storage=False, grav: float = GRAV,
-         check=True, donor_cell: bool = False, short_rk2: bool = False) -> List[np.ndarray]:
+         check=True, donor_cell: bool = False, short_rk2: bool = False,
+         time0: float = 0.0) -> List[np.ndarray]:
     """Advance a copy of the state's fields; returns the new five fields.
 
     donor_cell=True swaps the Koren face values for first-order upwind ones, a
     linear operator that exposes the RK3 stage structure in closed form (tests
     only; the model itself always uses the Koren limiter).  short_rk2=True
     takes the two-stage Runge-Kutta short step instead of the
-    forward-backward one."""
+    forward-backward one.  A state with a ``damping`` dict (nu_lat, nu_top,
+    bnd1, bnd2, t1, t2) is damped after every short step; time0 is the model
+    time at the start."""
     dt = s.dt if dt is None else dt
     n_long = s.n_long if n_long is None else n_long
     n_short = s.n_short if n_short is None else n_short
-    gh = _GridHolder(s, grav, donor_cell=donor_cell, short_rk2=short_rk2)
+    gh = _GridHolder(s, grav, donor_cell=donor_cell, short_rk2=short_rk2, time0=time0)
     f = [_f64(x).copy() for x in s.fields]
     rc = lib().or_step(gh.ref, _ptr_array(f), float(dt), int(n_long), int(n_short),
                        1 if f32_storage else 0)
@@ -260,3 +283,26 @@ def energy(s, fields=None, grav: float = GRAV) -> float:
     gh = _GridHolder(s, grav)
     f = [_f64(x) for x in (s.fields if fields is None else fields)]
     return lib().or_energy(gh.ref, _ptr_array(f))
+
+
+def diffuse(q, kx, ky, kz, steps: int = 1) -> np.ndarray:
+    """`steps` seven-point diffusion steps of q (shape (nz, ny, nx))."""
+    cur = _f64(q).copy()
+    nz, ny, nx = cur.shape
+    nxt = np.empty_like(cur)
+    for _ in range(steps):
+        rc = lib().or_diffuse(nx, ny, nz, float(kx), float(ky), float(kz), _ptr(cur), _ptr(nxt))
+        if rc != OK:
+            raise RuntimeError(rc)
+        cur, nxt = nxt, cur
+    return cur
+
+
+def damp(s, fields, dtau: float, t: float) -> List[np.ndarray]:
+    """The damping of one short step's end (state s must carry ``damping``)."""
+    gh = _GridHolder(s)
+    f = [_f64(x).copy() for x in fields]
+    rc = lib().or_damp(gh.ref, _ptr_array(f), float(dtau), float(t))
+    if rc != OK:
+        raise RuntimeError(rc)
+    return f

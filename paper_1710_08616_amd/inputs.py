@@ -158,6 +158,7 @@ class State:
     beta: float = 0.55
     name: str = ""
     terrain: Optional[np.ndarray] = None   # (ny, nx) surface heights; refs are 3D
+    damping: Optional[dict] = None         # lateral / upper damping data (see damping())
 
     @property
     def cells(self) -> int:
@@ -315,6 +316,46 @@ def rest_state(nx, ny, nz, dx=2000.0, dy=2000.0, zf=None, reference="isothermal"
 
 
 # --------------------------------------------------------------------------
+# lateral and upper damping data
+# --------------------------------------------------------------------------
+def damping(s: "State", width: int = 8, nu_lat: float = 1.0 / 60.0, z_start: float = 15000.0,
+            nu_top: float = 1.0 / 300.0, u1: float = 10.0, u2: float = 15.0, v2: float = 2.0,
+            theta_amp: float = 0.5, t1: float = 0.0, t2: float = 600.0) -> dict:
+    """Synthetic damping set-up for a state (boundary data stand in for a
+    parent model).
+
+    Rates: nu_lat (1 - d/width)^2 for columns d < width cells from the nearest
+    domain edge, nu_top sin^2(pi/2 (z - z_start)/(H - z_start)) for cell
+    centres above z_start.  Boundary states: at t1 a uniform wind u1 (U =
+    rho_u u1, rho_u the mean reference density of the face's two cells), at
+    t2 the wind
+    (u2, v2) with a Theta perturbation theta_amp rho_ref sin(2 pi x / Lx);
+    rho' = W = 0 in both.
+    """
+    nx, ny, nz = s.nx, s.ny, s.nz
+    i = np.arange(nx)[None, :]
+    j = np.arange(ny)[:, None]
+    d = np.minimum(np.minimum(i, nx - 1 - i), np.minimum(j, ny - 1 - j)).astype(np.float64)
+    lat = np.where(d < width, nu_lat * ((width - d) / width) ** 2, 0.0)
+    zc = centres(s.zf)
+    top = np.where(zc > z_start,
+                   nu_top * np.sin(0.5 * math.pi * (zc - z_start) / (s.zf[-1] - z_start)) ** 2, 0.0)
+    rho = s.rho_ref if np.ndim(s.rho_ref) == 3 else np.broadcast_to(
+        np.asarray(s.rho_ref)[:, None, None], (nz, ny, nx))
+    rho_u = 0.5 * (np.roll(rho, 1, axis=2) + rho)
+    rho_v = 0.5 * (np.roll(rho, 1, axis=1) + rho)
+    zero_c = np.zeros((nz, ny, nx))
+    zero_w = np.zeros((nz + 1, ny, nx))
+    xs = (np.arange(nx) + 0.5) / nx
+    b1 = [zero_c.copy(), rho_u * u1, zero_c.copy(), zero_w.copy(), zero_c.copy()]
+    b2 = [zero_c.copy(), rho_u * u2, rho_v * v2, zero_w.copy(),
+          theta_amp * rho * np.sin(2.0 * math.pi * xs)[None, None, :]]
+    return {"nu_lat": np.ascontiguousarray(lat), "nu_top": np.ascontiguousarray(top),
+            "bnd1": [np.ascontiguousarray(x) for x in b1],
+            "bnd2": [np.ascontiguousarray(x) for x in b2], "t1": float(t1), "t2": float(t2)}
+
+
+# --------------------------------------------------------------------------
 # named workloads
 # --------------------------------------------------------------------------
 C_SOUND = 347.2   # acoustic speed of the isothermal 300 K reference (m/s)
@@ -358,8 +399,9 @@ def workload(name: str) -> State:
                 of 10 long steps with 4 short steps per stage, dt = 10 s.
     large       1024x1024x64, 16 bubbles (r in 2..8 km), 100 long steps, n = 6.
     large_sub   128x128x64 sub-run of the same generator (oracle-sized).
-    xl          2048x2048x64, the same generator with 16 bubbles, 30 long steps,
-                n = 6 (the layout-comparison domain; flat lower boundary).
+    xl          2048x2048x64, the same generator with 16 bubbles over 8 Gaussian
+                hills (max 2 km), u = 10 m/s, 30 long steps, n = 6 (the
+                layout-comparison domain).
     terrain     1600x1280x64 over 8 Gaussian hills (max 2 km), 16 bubbles, wind
                 shear u = 30 z/H, 50 long steps, n = 6.
     terrain_sub 160x128x64 sub-run of the same generator (oracle-sized; hills
@@ -369,9 +411,10 @@ def workload(name: str) -> State:
         return make_state(64, 64, 32, seed=1710, dt=10.0, n_short=4, n_long=10, name=name)
     if name == "xl":
         seed = 1714
+        h = orography(2048, 2048, 2000.0, 2000.0, seed)
         bub = random_bubbles(seed, 16, 2048 * 2000.0, 2048 * 2000.0)
-        return make_state(2048, 2048, 64, seed=seed, bubbles=bub, dt=10.0, n_short=6,
-                          n_long=30, name=name)
+        return make_state(2048, 2048, 64, seed=seed, bubbles=bub, terrain=h, dt=10.0,
+                          n_short=6, n_long=30, name=name)
     if name in ("terrain", "terrain_sub"):
         nx, ny = (1600, 1280) if name == "terrain" else (160, 128)
         seed = 1712

@@ -1,13 +1,22 @@
 """Benchmark of the HEVI dynamical-core step on one GPU.
 
-Workload: the 1024x1024x64 warm-bubble domain (16 seeded bubbles of radius
-2-8 km, Gaussian velocity noise of 0.1 m/s in a 10 m/s wind, isothermal
-reference, dx = dy = 2 km, stretched levels to 20 km), RK3 long steps of
-dt = 10 s with 6 HEVI short steps per stage, periodic in x and y.  One
-"step" is one long step of the whole path: 3 slow sweeps, 18 short steps and
-the float64 mass sum.  The primary number is the float32 path; the mixed
+Default workload: the 1024x1024x64 warm-bubble domain (16 seeded bubbles of
+radius 2-8 km, Gaussian velocity noise of 0.1 m/s in a 10 m/s wind,
+isothermal reference, dx = dy = 2 km, stretched levels to 20 km), RK3 long
+steps of dt = 10 s with 6 HEVI short steps per stage, periodic in x and y.
+One "step" is one long step of the whole path: 3 slow sweeps, 18 short steps
+and the float64 mass sum.  The primary number is the float32 path; the mixed
 (float32 sweeps, float64 column solve) and float64 paths are timed on the same
 state for the speedup over the plain float64 step.
+
+Other workloads (--workload): terrain (1600x1280x64 over Gaussian hills with
+wind shear, mixed precision primary, error of each path against the float64
+GPU run), xl (2048x2048x64 over hills, for --layout kij / ijk), ensemble
+(48 members of uneven sizes), diffusion (the seven-point stencil of the
+paper's reduced weather application on 1024x1024x64, timed against its
+no-cache and perfect-cache bandwidth models).  --accuracy adds the per-field
+error of every path against the float64 oracle on the oracle-sized sub-run of
+the workload.
 
 Prints one JSON line.  Progress goes to stderr.
 """
@@ -34,11 +43,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def model_bytes_per_cell(b: int, n_short: int) -> int:
+def model_bytes_per_cell(b: int, n_short: int, terrain: bool = False) -> int:
     """Compulsory bytes per cell per long step: 3 slow sweeps (read 5 state,
-    write 7), 3*n short steps (read 5 state + 4 tendencies + 3 stage
-    coefficients, write 5), one mass sum (read rho')."""
-    return b * (3 * 12 + 3 * n_short * 17 + 1)
+    write 7; over terrain also read the 3 per-cell reference fields),
+    3*n short steps (read 5 state + 4 tendencies + 3 stage coefficients,
+    write 5), one mass sum (read rho')."""
+    return b * (3 * (15 if terrain else 12) + 3 * n_short * 17 + 1)
 
 
 def short_step_bytes(b: int, cells: int) -> int:
@@ -67,10 +77,10 @@ def read_traffic(prec: str):
     return None
 
 
-def time_precision(hevi, s, prec, steps, warmup, layout="kij"):
+def time_precision(hevi, s, prec, steps, warmup, layout="kij", keep=False, short="fb"):
     import torch
     log(f"[bench] {prec}: init {s.nx}x{s.ny}x{s.nz}")
-    d = hevi.Domain(s, precision=prec, layout=layout)
+    d = hevi.Domain(s, precision=prec, layout=layout, short=short)
     if warmup:
         d.step(s.dt, warmup, s.n_short)
     m0 = d.mass()
@@ -93,6 +103,7 @@ def time_precision(hevi, s, prec, steps, warmup, layout="kij"):
     kern = d.trace_read()
     d.trace(False)
     m1 = d.mass()
+    final = d.read_all() if keep else None
     d.close()
     del d
     torch.cuda.empty_cache()
@@ -101,7 +112,8 @@ def time_precision(hevi, s, prec, steps, warmup, layout="kij"):
         "ms_per_step": ms / steps,
         "graph_ms_per_step": graph_ms / steps,
         "cell_updates_per_s": cells * steps / (ms * 1e-3),
-        "model_gbps": model_bytes_per_cell(BYTES[prec], s.n_short) * cells * steps / (ms * 1e-3) / 1e9,
+        "model_gbps": model_bytes_per_cell(BYTES[prec], s.n_short, s.terrain is not None)
+        * cells * steps / (ms * 1e-3) / 1e9,
         "mass_drift_rel": abs(m1 - m0) / m0,
         "kernels_ms_avg": {k: (v[0] / v[1] if v[1] else None) for k, v in kern.items()},
         "kernels_launches": {k: v[1] for k, v in kern.items()},
@@ -109,7 +121,40 @@ def time_precision(hevi, s, prec, steps, warmup, layout="kij"):
     }
     log(f"[bench] {prec}: {res['ms_per_step']:.3f} ms/step (graph replay {res['graph_ms_per_step']:.3f}), "
         f"{res['cell_updates_per_s']:.3e} cell-updates/s, model {res['model_gbps']:.0f} GB/s")
-    return res
+    return (res, final) if keep else res
+
+
+def field_errors(got, ref):
+    """Per field: max and RMS of (got - ref), each divided by the range of ref."""
+    from paper_1710_08616_amd import inputs
+    out = {}
+    for name, a, b in zip(inputs.FIELD_NAMES, got, ref):
+        rng = float(np.ptp(b)) or 1.0
+        d = a - b
+        out[name] = {"max_rel": float(np.abs(d).max()) / rng,
+                     "rms_rel": float(np.sqrt(np.mean(d * d))) / rng}
+    return out
+
+
+def accuracy_vs_oracle(hevi, sub, precs):
+    """Every path against the float64 oracle on an oracle-sized sub-run of the
+    workload (same generator), after its full number of long steps."""
+    from oracle import oracle
+    log(f"[bench] accuracy: oracle {sub.nx}x{sub.ny}x{sub.nz}, {sub.n_long} long steps")
+    t0 = time.perf_counter()
+    ref = oracle.step(sub)
+    log(f"[bench] accuracy: oracle took {time.perf_counter() - t0:.1f} s")
+    out = {}
+    for p in precs:
+        d = hevi.Domain(sub, precision=p)
+        m0 = d.mass()
+        d.step(sub.dt, sub.n_long, sub.n_short)
+        got = d.read_all()
+        m1 = d.mass()
+        d.close()
+        out[p] = {"fields": field_errors(got, ref), "mass_drift_rel": abs(m1 - m0) / m0}
+    return {"sub_run": f"{sub.nx}x{sub.ny}x{sub.nz}, {sub.n_long} long steps, n={sub.n_short}",
+            "per_precision": out}
 
 
 def time_ensemble(hevi, members, prec, steps, warmup, layout="kij", tune=True):
@@ -164,21 +209,69 @@ def time_ensemble(hevi, members, prec, steps, warmup, layout="kij", tune=True):
     return res
 
 
-def cpu_baseline(steps: int = 4, n: int = 512):
+def time_diffusion(hevi, prec, steps, warmup, layout="kij", n=1024, nz=64):
+    """hv_diffuse on an n x n x nz field, each tile shape; the fastest is kept.
+    Bytes per cell and step: perfect cache 2b (one read, one write), no
+    cache 8b (7 reads, 1 write)."""
+    import torch
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    b = 4 if prec == "fp32" else 8
+    shape = (n, n, nz) if layout == "kij" else (nz, n, n)
+    g = torch.Generator(device="cuda").manual_seed(1716)
+    x = torch.rand(shape, generator=g, device="cuda", dtype=dt) + 1.0
+    y = torch.empty_like(x)
+    k = (0.1, 0.1, 0.2)
+    best = None
+    for tile in (16, 8, 4):
+        for _ in range(warmup):
+            hevi.diffuse(x, y, *k, layout=layout, tile_x=tile)
+            x, y = y, x
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            hevi.diffuse(x, y, *k, layout=layout, tile_x=tile)
+            x, y = y, x
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        log(f"[bench] diffusion {prec} {layout} tile {tile}: {ms:.4f} ms/step")
+        if best is None or ms < best[1]:
+            best = (tile, ms)
+    cells = n * n * nz
+    tile, ms = best
+    t_perfect = 2 * b * cells / (HBM_PEAK_GBS * 1e9) * 1e3
+    t_nocache = 8 * b * cells / (HBM_PEAK_GBS * 1e9) * 1e3
+    return {"ms_per_step": ms, "tile_x": tile, "cells": cells,
+            "cell_updates_per_s": cells / (ms * 1e-3),
+            "perfect_cache_gbps": 2 * b * cells / (ms * 1e-3) / 1e9,
+            "frac_of_perfect_cache_limit": t_perfect / ms,
+            "speedup_vs_no_cache_model": t_nocache / ms}
+
+
+def cpu_baseline(steps: int = 4, n: int = 512, terrain: bool = False):
     """The FP64 oracle on a bounded sample of the same workload: an n x n x 64
-    domain from the same generator (16 bubbles), `steps` long steps."""
+    domain from the same generator (16 bubbles; over hills with shear for the
+    terrain workload), `steps` long steps."""
     from oracle import oracle
     from paper_1710_08616_amd import inputs
-    bub = inputs.random_bubbles(1711, 16, n * 2000.0, n * 2000.0)
-    s = inputs.make_state(n, n, 64, seed=1711, bubbles=bub, dt=10.0, n_short=6)
+    seed = 1712 if terrain else 1711
+    bub = inputs.random_bubbles(seed, 16, n * 2000.0, n * 2000.0)
+    if terrain:
+        h = inputs.orography(n, n, 2000.0, 2000.0, seed)
+        s = inputs.make_state(n, n, 64, seed=seed, bubbles=bub, u_bg=0.0, shear=30.0, terrain=h,
+                              dt=10.0, n_short=6)
+    else:
+        s = inputs.make_state(n, n, 64, seed=seed, bubbles=bub, dt=10.0, n_short=6)
     oracle.lib()
     t0 = time.perf_counter()
     oracle.step(s, n_long=steps)
     sec = time.perf_counter() - t0
     return {"value": s.cells * steps / sec, "unit": "cell-updates/s", "cores": oracle.threads(),
             "kind": "oracle",
-            "sample": f"{n}x{n}x64 sub-domain of the same generator, {steps} long steps "
-                      f"(n=6), {sec:.1f} s"}
+            "sample": f"{n}x{n}x64 domain of the same generator{' over hills' if terrain else ''}, "
+                      f"{steps} long steps (n=6), {sec:.1f} s"}
 
 
 def main():
@@ -186,11 +279,20 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precisions", default="fp32,mixed,fp64")
+    ap.add_argument("--precisions", default=None,
+                    help="default: fp32,mixed,fp64 (terrain: mixed,fp64; xl: fp32,mixed)")
     ap.add_argument("--layout", default="kij")
     ap.add_argument("--workload", default="large")
+    ap.add_argument("--short", default="fb", choices=["fb", "rk2"],
+                    help="short-step integrator: forward-backward or two-stage Runge-Kutta")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--accuracy", action="store_true",
+                    help="per-field error of every path against the float64 oracle on the "
+                         "oracle-sized sub-run")
     args = ap.parse_args()
+    if args.precisions is None:
+        args.precisions = {"terrain": "mixed,fp64", "xl": "fp32,mixed", "ensemble": "fp32,mixed",
+                           "diffusion": "fp32,fp64"}.get(args.workload, "fp32,mixed,fp64")
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the step is built and measured on a single "
@@ -202,6 +304,41 @@ def main():
     from paper_1710_08616_amd import hevi, inputs
     hevi.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    if args.workload == "diffusion":
+        precs = [p for p in args.precisions.split(",") if p and p != "mixed"] or ["fp32"]
+        res = {p: time_diffusion(hevi, p, args.steps, args.warmup, args.layout) for p in precs}
+        r = res[precs[0]]
+        b = 4 if precs[0] == "fp32" else 8
+        cpu = None
+        if not args.no_cpu_baseline:
+            from oracle import oracle
+            q = np.random.default_rng(1716).random((64, 512, 512)) + 1.0
+            oracle.lib()
+            t0 = time.perf_counter()
+            oracle.diffuse(q, 0.1, 0.1, 0.2, steps=20)
+            sec = time.perf_counter() - t0
+            cpu = {"value": q.size * 20 / sec, "unit": "cell-updates/s", "cores": oracle.threads(),
+                   "kind": "oracle", "sample": f"512x512x64, 20 steps, {sec:.1f} s"}
+        out = {
+            "metric": METRIC, "value": r["cell_updates_per_s"], "unit": "cell-updates/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32" if precs[0] == "fp32" else "f64",
+            "data": "synthetic",
+            "config": {"workload": "seven-point diffusion 1024x1024x64 (bandwidth-model stencil)",
+                       "precision": precs[0], "layout": args.layout, "tile_x": r["tile_x"],
+                       "parallelism": "1 GPU"},
+            "roofline": {"bound": "hbm", "achieved": round(r["perfect_cache_gbps"], 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(r["perfect_cache_gbps"] / HBM_PEAK_GBS, 4), "traffic": None,
+                         "kernel": "diffuse", "bytes_per_launch": 2 * b * r["cells"],
+                         "launch_ms_avg": round(r["ms_per_step"], 4)},
+            "cpu_baseline": cpu,
+            "per_precision": res,
+        }
+        print(json.dumps(out), flush=True)
+        return
 
     if args.workload == "ensemble":
         t0 = time.time()
@@ -231,10 +368,26 @@ def main():
     s = inputs.workload(args.workload)
     log(f"[bench] state {s.nx}x{s.ny}x{s.nz} generated in {time.time() - t0:.1f} s")
     precs = [p for p in args.precisions.split(",") if p]
-    res = {p: time_precision(hevi, s, p, args.steps, args.warmup, args.layout) for p in precs}
+    terrain = s.terrain is not None
+    # over terrain, every path is also compared with the float64 GPU run
+    # (all paths take the same number of long steps from the same state)
+    keep = terrain and "fp64" in precs and len(precs) > 1
+    res, finals = {}, {}
+    for p in precs:
+        r = time_precision(hevi, s, p, args.steps, args.warmup, args.layout, keep=keep,
+                           short=args.short)
+        if keep:
+            r, finals[p] = r
+        res[p] = r
+    errors_vs_fp64 = None
+    if keep:
+        errors_vs_fp64 = {p: field_errors(finals[p], finals["fp64"]) for p in precs if p != "fp64"}
+        finals.clear()
     primary = "fp32" if "fp32" in res else precs[0]
     r = res[primary]
     b = BYTES[primary]
+    # one launch of the short-step kernel (the Runge-Kutta form launches it
+    # twice per short step, the second reading 3 more fields)
     short_ms = r["kernels_ms_avg"]["short_step"]
     ach = short_step_bytes(b, s.cells) / (short_ms * 1e-3) / 1e9
     traffic = read_traffic(primary)
@@ -245,8 +398,12 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle baseline")
-        cpu = cpu_baseline()
+        cpu = cpu_baseline(terrain=terrain)
         log(f"[bench] oracle: {cpu['value']:.3e} cell-updates/s on {cpu['cores']} threads")
+    accuracy = None
+    if args.accuracy:
+        sub = {"large": "large_sub", "terrain": "terrain_sub"}.get(args.workload, "small")
+        accuracy = accuracy_vs_oracle(hevi, inputs.workload(sub), precs)
     out = {
         "metric": METRIC,
         "value": r["cell_updates_per_s"],
@@ -260,16 +417,22 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if primary == "fp32" else ("f32+f64" if primary == "mixed" else "f64"),
         "data": "synthetic",
-        "config": {"workload": f"{s.nx}x{s.ny}x{s.nz} warm bubbles + noise, dt=10 s, "
-                               f"{s.n_short} short steps/stage",
+        "config": {"workload": f"{s.nx}x{s.ny}x{s.nz} warm bubbles + noise"
+                               f"{' over Gaussian hills (max 2 km), shear 0-30 m/s' if terrain else ''}"
+                               f", dt=10 s, {s.n_short} short steps/stage",
                    "nx": s.nx, "ny": s.ny, "nz": s.nz, "n_short": s.n_short, "dt": s.dt,
-                   "precision": primary, "layout": args.layout, "parallelism": "1 GPU"},
+                   "precision": primary, "layout": args.layout, "short_step": args.short,
+                   "parallelism": "1 GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "model_gbps": r["model_gbps"],
         "model_frac_of_peak": r["model_gbps"] / HBM_PEAK_GBS,
         "per_precision": res,
     }
+    if errors_vs_fp64 is not None:
+        out["errors_vs_fp64_gpu"] = errors_vs_fp64
+    if accuracy is not None:
+        out["accuracy_vs_oracle"] = accuracy
     if "fp64" in res:
         for p in res:
             if p != "fp64":

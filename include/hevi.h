@@ -75,6 +75,17 @@ enum { HV_FP64 = 0, HV_FP32 = 1, HV_MIXED = 2 };
  * kernels with strided column access, for layout comparisons. */
 enum { HV_IJK = 0, HV_KIJ = 1 };
 
+/* Short-step integrator.  HV_SHORT_FB: forward-backward HEVI step
+ * (horizontal momentum first, then the divergences of the new momentum and
+ * the beta-off-centred vertical coupling; one column solve).  HV_SHORT_RK2:
+ * the paper's second-order Runge-Kutta short step (Sect. 1.1), read as the
+ * midpoint rule over that step: X* = Phi(X, X, dtau/2), X+ = Phi(X, X*, dtau),
+ * where Phi(X_b, X_e, d) adds its increments to X_b and takes p' of the
+ * horizontal pressure gradient and the old-time (1 - beta) parts of the
+ * vertical coupling from X_e; two column solves per short step, damping for
+ * sound waves where the forward-backward step is neutral. */
+enum { HV_SHORT_FB = 0, HV_SHORT_RK2 = 1 };
+
 /* Field ids for hv_state_read. */
 enum { HV_RHO_PTB = 0, HV_RHOU = 1, HV_RHOV = 2, HV_RHOW = 3, HV_RHOTHETA_PTB = 4 };
 
@@ -89,6 +100,8 @@ typedef struct {
     int32_t layout;            /* HV_KIJ or HV_IJK                           */
     double beta;               /* off-centring of the vertical solve, in [0.5, 1] */
     double div_damp;           /* must be 0                                  */
+    int32_t short_scheme;      /* HV_SHORT_FB or HV_SHORT_RK2                */
+    int32_t damping;           /* 1: reserve workspace for hv_damping        */
 } hv_grid_desc;
 
 /* Bytes of device workspace the grid needs; 0 if the description is invalid
@@ -142,7 +155,8 @@ int hv_mass(hv_grid_t g, double *mass_out, double *energy_out);
  * per-kind totals and returns the total milliseconds and launch count of
  * one kind (a "launch" of HV_K_MASS is its two-kernel reduction).  Either
  * output pointer may be NULL. */
-enum { HV_K_SLOW_PREP = 0, HV_K_SLOW_FLUX = 1, HV_K_SHORT_STEP = 2, HV_K_MASS = 3, HV_K_COUNT = 4 };
+enum { HV_K_SLOW_PREP = 0, HV_K_SLOW_FLUX = 1, HV_K_SHORT_STEP = 2, HV_K_MASS = 3, HV_K_DAMP = 4,
+       HV_K_COUNT = 5 };
 int hv_trace(hv_grid_t g, int32_t on);
 int hv_trace_read(hv_grid_t g, int32_t kind, double *ms_total, int64_t *launches);
 
@@ -154,6 +168,27 @@ int hv_trace_read(hv_grid_t g, int32_t kind, double *ms_total, int64_t *launches
  * tile_x_out (may be NULL) receives the chosen x-extent of the three kinds.
  * Synchronises the stream; does not change the state. */
 int hv_tune(hv_grid_t g, int32_t *tile_x_out);
+
+/* Lateral and upper damping, the relaxation kernel of the paper's Listing 1
+ * (Sect. 3), applied after every short step.  The target of each prognostic
+ * is the boundary state interpolated in time,
+ *   X_target = mtratio (ref + bnd1) + tratio (ref + bnd2) - ref,
+ * tratio = (t - t1)/(t2 - t1) clipped to [0, 1], mtratio = 1 - tratio, ref the
+ * reference rho or rho*theta for HV_RHO_PTB / HV_RHOTHETA_PTB and 0 for the
+ * momenta, t the model time at the end of the short step.  Each value then
+ * relaxes implicitly, X <- (X + c X_target)/(1 + c), c = dtau (nu_lat of its
+ * column + nu_top of its level; W's level face k uses level k); values with
+ * rate 0 and W on the lids are left untouched.
+ * Arguments: nu_lat nx*ny rates (1/s, >= 0, i fastest), nu_top nz rates;
+ * bnd1[f], bnd2[f] boundary states in the layout of hv_state_init's fields
+ * (W with zero lids); t1 < t2; time_now = model time of the current state
+ * (it advances by dt per long step; hv_state_init resets it to 0).  Host
+ * arrays are copied (converted to the grid's precision and layout) into the
+ * workspace, which must have been sized with desc.damping = 1, else
+ * HV_ERR_ARG.  Replaces earlier damping data; synchronises the stream. */
+int hv_damping(hv_grid_t g, const double *nu_lat, const double *nu_top,
+               const double *const bnd1[5], const double *const bnd2[5], double t1, double t2,
+               double time_now);
 
 /* Release the handle (never the caller's workspace).  NULL is a no-op. */
 void hv_grid_destroy(hv_grid_t g);
@@ -185,10 +220,31 @@ int hv_ens_mass(hv_ens_t e, int32_t member, double *mass_out, double *energy_out
 /* As hv_tune, per group of members with equal nz (groups in increasing nz):
  * tile_x_out receives 3 entries per group, *ngroups_out the group count. */
 int hv_ens_tune(hv_ens_t e, int32_t *tile_x_out, int32_t *ngroups_out);
+int hv_ens_damping(hv_ens_t e, int32_t member, const double *nu_lat, const double *nu_top,
+                   const double *const bnd1[5], const double *const bnd2[5], double t1, double t2,
+                   double time_now);
 int hv_ens_trace(hv_ens_t e, int32_t on);
 int hv_ens_trace_read(hv_ens_t e, int32_t kind, double *ms_total, int64_t *launches);
 void hv_ens_destroy(hv_ens_t e);
 const char *hv_ens_last_error(hv_ens_t e);
+
+/* ---------------------------------------------------------------------------
+ * Seven-point diffusion step: the stencil whose memory traffic dominates the
+ * paper's reduced weather application and its no-cache / perfect-cache
+ * bandwidth model (Sect. 4).  One explicit step on a uniform grid,
+ *   out = q + ((kx lx + ky ly) + kz lz),  l_d = (q_{-d} + q_{+d}) - 2 q,
+ * kd = nu dt / d^2, periodic in x and y, no flux through the lids (the
+ * missing vertical neighbour is the cell itself).
+ * dev_in, dev_out: device arrays of nx*ny*nz values of the precision's type
+ * (HV_FP64: double, HV_FP32: float; HV_MIXED is HV_ERR_ARG) in `layout`
+ * (HV_KIJ: k + nz*(i + nx*j); HV_IJK: i + nx*(j + ny*k)), 64-byte aligned,
+ * distinct; owned by the caller.  nz in {32, 64, 128}.  tile_x: 16, 8 or 4
+ * columns along x per 256-thread block.  Enqueued on hip_stream (NULL = the
+ * default stream); asynchronous.  Invalid arguments return HV_ERR_ARG before
+ * any launch (text in hv_last_error(NULL)). */
+int hv_diffuse(int32_t nx, int32_t ny, int32_t nz, int32_t precision, int32_t layout, double kx,
+               double ky, double kz, int32_t tile_x, const void *dev_in, void *dev_out,
+               void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -49,12 +49,18 @@ struct MemberDev {
     double rdx, rdy, beta, dt;   // dt: long step of this member
     const double *vm;
     double *partials;
-    double *sums;                // [0] perturbation mass, [1] energy
-    void *st[3][5];              // rho', U, V, W, Theta' of the three buffers
+    double *sums;                // [0] perturbation mass, [1] energy, [2] model time
+    void *st[4][5];              // rho', U, V, W, Theta' of the state buffers
+                                 // ([3]: first-stage value of the Runge-Kutta short step)
     void *slow[7];               // S_U, S_V, S_W, R_Theta, theta_s, P0_s, C_s
     void *spec[4];               // u, v, w of the stage input; [3] Omega (terrain)
     const double *geo;           // terrain: GEO_NFIELDS per column, else null
     void *ref[3];                // terrain: rho_ref, rhotheta_ref, p_ref per cell
+    // lateral / upper damping (nu_lat null: none)
+    const double *nu_lat;        // per column (nx*ny)
+    const double *nu_top;        // per level (nz)
+    void *bnd[2][5];             // boundary states at t1 and t2 (device layout)
+    double t1, t2;
 };
 
 // One launch over the blocks of a group of members (all with the same nz).
@@ -69,6 +75,7 @@ struct Group {
     int nblocks;            // blocks of the launch
     int ti_log2;            // tile = (1 << ti_log2) columns along x by 16 >> ti_log2 along y
     int src, dst;           // state buffers read and written by this launch
+    int ev;                 // short step: buffer of the explicit / old-time terms (src: forward-backward)
     int terrain;            // members of the group are terrain-following
 };
 
@@ -89,10 +96,27 @@ inline int partials_of(int nx, int ny)
 // Slow sweep of stage `stage` on buffer gr.src.
 hipError_t launch_slow_prep(int prec, int layout, int L, const Group &gr, hipStream_t s);
 hipError_t launch_slow_flux(int prec, int layout, int L, const Group &gr, hipStream_t s);
-// Short step gr.src -> gr.dst of length (member dt) * frac.
+// Short step gr.src -> gr.dst of length (member dt) * frac, explicit and
+// old-time terms from gr.ev.
 hipError_t launch_short_step(int prec, int layout, int L, const Group &gr, double frac, hipStream_t s);
+// Lateral and upper damping of buffer gr.src in place, at model time
+// sums[2] + offset * dt, after a short step of length dt * frac.
+hipError_t launch_damp(int prec, int layout, int L, const Group &gr, double offset, double frac,
+                       hipStream_t s);
+// One thread per member of the group: model time += dt (end of a long step).
+hipError_t launch_clock(const Group &gr, hipStream_t s);
 // gr.blk maps blocks to (member, partial).  Sums the perturbation mass
 // (energy = false) or the total energy of buffer gr.src into each member's sums.
 hipError_t launch_sums(int prec, int layout, int L, const Group &gr, bool energy, hipStream_t s);
+
+// Seven-point diffusion step on one device array (nx*ny*nz values of type
+// prec 0 = double, 1 = float, in `layout`): out = q + kx lx + ky ly + kz lz.
+struct DiffArgs {
+    int nx, ny, nz, ti_log2;
+    double kx, ky, kz;
+    const void *in;
+    void *out;
+};
+hipError_t launch_diffuse(int prec, int layout, int L, const DiffArgs &a, hipStream_t s);
 
 }  // namespace hv

@@ -199,26 +199,47 @@ template <> __device__ __forceinline__ float xexpm1<float>(float x) { return exp
 template <typename T> __device__ __forceinline__ T xlog1p(T x) { return log1p(x); }
 template <> __device__ __forceinline__ float xlog1p<float>(float x) { return log1pf(x); }
 
-// Koren increment psi(D+/D-) * D- without the division:
+// Half the Koren increment, psi(D+/D-) D- / 2, without the division:
 // psi(r) = max(0, min(2r, (1 + 2r)/3, 2))  (Koren 1993, kappa = 1/3).
+// Written sign-symmetrically: with s = sign(D-), a = |D-| and b = s D+,
+//   psi D- / 2 = s max(0, min(b, (a + 2b)/6, a)),
+// and D- = 0 gives 0.  Both signs share one min/max chain, and the halving
+// is folded into exact power-of-two scalings (1/6 = (1/3)/2 exactly), so the
+// value equals q1 + 0.5 * (the two-branch form) bit for bit.
+template <typename T> struct SignBits;
+template <> struct SignBits<float> {
+    using U = unsigned;
+    static constexpr U kSign = 0x80000000u;
+};
+template <> struct SignBits<double> {
+    using U = unsigned long long;
+    static constexpr U kSign = 0x8000000000000000ull;
+};
+
 template <typename T>
-__device__ __forceinline__ T koren_phi(T dm, T dp)
+__device__ __forceinline__ T koren_half(T dm, T dp)
 {
-    const T t = (dm + T(2) * dp) * T(1.0 / 3.0);
-    const T pos = fmax(T(0), fmin(fmin(T(2) * dp, t), T(2) * dm));
-    const T neg = fmin(T(0), fmax(fmax(T(2) * dp, t), T(2) * dm));
-    return dm > T(0) ? pos : (dm < T(0) ? neg : T(0));
+    using U = typename SignBits<T>::U;
+    const U sgn = __builtin_bit_cast(U, dm) & SignBits<T>::kSign;
+    const T a = fabs(dm);
+    const T b = __builtin_bit_cast(T, __builtin_bit_cast(U, dp) ^ sgn);
+    const T t = (a + (b + b)) * T(1.0 / 6.0);
+    const T v = fmax(T(0), fmin(fmin(b, t), a));
+    return __builtin_bit_cast(T, __builtin_bit_cast(U, v) ^ sgn);
 }
 
-// Limited face value between L and R for mass flux m (m >= 0: from L).
+// Limited face value between L and R for mass flux m (m >= 0: from L).  The
+// downwind-side differences for m < 0 are the negated upwind ones
+// (x - y = -(y - x) exactly).
 template <typename T>
 __device__ __forceinline__ T kface(T qLL, T qL, T qR, T qRR, T m)
 {
     const bool up = m >= T(0);
-    const T q0 = up ? qLL : qRR;
+    const T d1 = qR - qL;
+    const T dm = up ? qL - qLL : -(qRR - qR);
+    const T dp = up ? d1 : -d1;
     const T q1 = up ? qL : qR;
-    const T q2 = up ? qR : qL;
-    return q1 + T(0.5) * koren_phi(q1 - q0, q2 - q1);
+    return q1 + koren_half(dm, dp);
 }
 
 // --------------------------------------------------------------------------
@@ -747,13 +768,14 @@ __device__ __forceinline__ void segment_solve(int p, const S (&A)[L], const S (&
 
 // Occupancy target of the short step (waves per SIMD), chosen so that the
 // register budget holds the lane's levels without spilling: 4 in float32
-// (3 with the terrain terms), 2 with a float64 solve (1 for float64 storage
-// with the terrain terms), 1 for 8 levels per lane.
-template <typename T, typename S, int L, bool TR>
+// (3 with the terrain terms or a separate evaluation state), 2 with a
+// float64 solve (1 for float64 storage with the terrain terms), 1 for 8
+// levels per lane.
+template <typename T, typename S, int L, bool TR, bool EV>
 constexpr int short_waves()
 {
     if (L >= 8) return 1;
-    if (sizeof(T) == 4 && sizeof(S) == 4) return TR ? 3 : 4;
+    if (sizeof(T) == 4 && sizeof(S) == 4) return (TR || EV) ? 3 : 4;
     if (sizeof(T) == 8 && TR && L >= 4) return 1;
     return 2;
 }
@@ -779,17 +801,24 @@ __device__ __forceinline__ void ddzeta(const T (&pp)[L], const T (&rdzf)[L], int
     }
 }
 
-template <typename T, typename S, class Lay, int L, bool TR>
+// EV: the explicit terms (p' of the horizontal pressure gradient) and the
+// old-time (1 - beta) parts of the vertical coupling come from a second state
+// (rpE, WE, tpE), while the increments are added to the first (rp, U, V, W,
+// tp): the second stage of the Runge-Kutta short step.  Without EV both are
+// the input state (forward-backward step).
+template <typename T, typename S, class Lay, int L, bool TR, bool EV>
 __device__ __forceinline__ void short_body(
     const Lane<Lay, L> &ln, const double *__restrict__ vm, const double *__restrict__ geo,
     double dtau_d, double beta_d, T rdx, T rdy,
     const T *__restrict__ rp, const T *__restrict__ U, const T *__restrict__ V,
-    const T *__restrict__ W, const T *__restrict__ tp, T *__restrict__ rpo, T *__restrict__ Uo,
+    const T *__restrict__ W, const T *__restrict__ tp, const T *__restrict__ rpE,
+    const T *__restrict__ WE, const T *__restrict__ tpE, T *__restrict__ rpo, T *__restrict__ Uo,
     T *__restrict__ Vo, T *__restrict__ Wo, T *__restrict__ tpo, const T *__restrict__ SU,
     const T *__restrict__ SV, const T *__restrict__ SW, const T *__restrict__ RT,
     const T *__restrict__ ths, const T *__restrict__ P0, const T *__restrict__ Cs)
 {
     const T dt = (T)dtau_d;
+    const T *__restrict__ tpx = EV ? tpE : tp;   // Theta' of the pressure
 
     // ---- horizontally explicit part (storage precision) ----
     T pc[L], pw[L], pe[L], ps[L], pn[L];
@@ -798,19 +827,25 @@ __device__ __forceinline__ void short_body(
         T a[L], c[L], t[L];
         ln.load(P0, 0, 0, P0c);
         ln.load(Cs, 0, 0, Csc);
-        ln.load(tp, 0, 0, tpc);
+        ln.load(tpx, 0, 0, t);
 #pragma unroll
-        for (int l = 0; l < L; ++l) pc[l] = P0c[l] + Csc[l] * tpc[l];
-        ln.load(P0, -1, 0, a); ln.load(Cs, -1, 0, c); ln.load(tp, -1, 0, t);
+        for (int l = 0; l < L; ++l) pc[l] = P0c[l] + Csc[l] * t[l];
+        if constexpr (EV) {
+            ln.template load<true>(tp, 0, 0, tpc);
+        } else {
+#pragma unroll
+            for (int l = 0; l < L; ++l) tpc[l] = t[l];
+        }
+        ln.load(P0, -1, 0, a); ln.load(Cs, -1, 0, c); ln.load(tpx, -1, 0, t);
 #pragma unroll
         for (int l = 0; l < L; ++l) pw[l] = a[l] + c[l] * t[l];
-        ln.load(P0, 1, 0, a); ln.load(Cs, 1, 0, c); ln.load(tp, 1, 0, t);
+        ln.load(P0, 1, 0, a); ln.load(Cs, 1, 0, c); ln.load(tpx, 1, 0, t);
 #pragma unroll
         for (int l = 0; l < L; ++l) pe[l] = a[l] + c[l] * t[l];
-        ln.load(P0, 0, -1, a); ln.load(Cs, 0, -1, c); ln.load(tp, 0, -1, t);
+        ln.load(P0, 0, -1, a); ln.load(Cs, 0, -1, c); ln.load(tpx, 0, -1, t);
 #pragma unroll
         for (int l = 0; l < L; ++l) ps[l] = a[l] + c[l] * t[l];
-        ln.load(P0, 0, 1, a); ln.load(Cs, 0, 1, c); ln.load(tp, 0, 1, t);
+        ln.load(P0, 0, 1, a); ln.load(Cs, 0, 1, c); ln.load(tpx, 0, 1, t);
 #pragma unroll
         for (int l = 0; l < L; ++l) pn[l] = a[l] + c[l] * t[l];
     }
@@ -866,9 +901,20 @@ __device__ __forceinline__ void short_body(
     ln.load(V, 0, 1, V1);
     ln.load(SV, 0, 0, SV0);
     ln.load(SV, 0, 1, SV1);
-    T rpc[L], Wc[L], SWc[L], RTc[L];
+    // rpc, Wbc: the state the increments are added to; rpo_, Wc: old-time values
+    T rpc[L], rpold[L], Wc[L], Wbc[L], SWc[L], RTc[L];
     ln.template load<true>(rp, 0, 0, rpc);
-    ln.template load<true>(W, 0, 0, Wc);
+    ln.template load<true>(EV ? WE : W, 0, 0, Wc);
+    if constexpr (EV) {
+        ln.template load<true>(rpE, 0, 0, rpold);
+        ln.template load<true>(W, 0, 0, Wbc);
+    } else {
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            rpold[l] = rpc[l];
+            Wbc[l] = Wc[l];
+        }
+    }
     ln.template load<true>(SW, 0, 0, SWc);
     ln.template load<true>(RT, 0, 0, RTc);
 
@@ -973,7 +1019,7 @@ __device__ __forceinline__ void short_body(
         }
         Cc[l] = (S)Csc[l];
         pE[l] = be * ((S)P0c[l] + Cc[l] * thE[l]) + one_m_be * (S)pc[l];
-        rEs[l] = be * rhE[l] + one_m_be * (S)rpc[l];
+        rEs[l] = be * rhE[l] + one_m_be * (S)rpold[l];
     }
     const S C_b = from_below(Cc[L - 1]), thf_b = from_below(thf[L - 1]);
     const S pE_b = from_below(pE[L - 1]), rEs_b = from_below(rEs[L - 1]);
@@ -992,7 +1038,7 @@ __device__ __forceinline__ void short_body(
         const S fC = -mu * Cc[l] * thf[l + 1] * (rdzf[l] * rdzp) - mu * grav * av[l] * rdzp;
         const S fB = S(1) + mu * thf[l] * (Cc[l] * rdzp + Cm * rdzm) * rdzf[l] +
                      mu * grav * (av[l] * rdzp - bv[l] * rdzm);
-        const S fD = Wf[l] + dts * (S)SWc[l] - (dts * rdzf[l]) * (pE[l] - pEm) -
+        const S fD = (S)Wbc[l] + dts * (S)SWc[l] - (dts * rdzf[l]) * (pE[l] - pEm) -
                      dts * grav * (av[l] * rEs[l] + bv[l] * rEm);
         const bool lid = (k == 0);
         A[l] = lid ? S(0) : fA;
@@ -1019,22 +1065,94 @@ __device__ __forceinline__ void short_body(
     ln.store(tpo, tpn);
 }
 
-template <typename T, typename S, class Lay, int L, bool TR>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(short_waves<T, S, L, TR>())))
+template <typename T, typename S, class Lay, int L, bool TR, bool EV>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(short_waves<T, S, L, TR, EV>())))
 void k_short_step(Group gr, double frac)
 {
     const Where wh = locate(gr);
     if (!wh.active) return;
     const MemberDev *m = wh.m;
     const Lane<Lay, L> ln(m->nx, m->ny, m->nz, wh.i, wh.j);
-    short_body<T, S, Lay, L, TR>(
+    short_body<T, S, Lay, L, TR, EV>(
         ln, m->vm, m->geo, m->dt * frac, m->beta, (T)m->rdx, (T)m->rdy,
         (const T *)buf(m, gr.src, 0), (const T *)buf(m, gr.src, 1), (const T *)buf(m, gr.src, 2),
-        (const T *)buf(m, gr.src, 3), (const T *)buf(m, gr.src, 4), (T *)buf(m, gr.dst, 0),
+        (const T *)buf(m, gr.src, 3), (const T *)buf(m, gr.src, 4), (const T *)buf(m, gr.ev, 0),
+        (const T *)buf(m, gr.ev, 3), (const T *)buf(m, gr.ev, 4), (T *)buf(m, gr.dst, 0),
         (T *)buf(m, gr.dst, 1), (T *)buf(m, gr.dst, 2), (T *)buf(m, gr.dst, 3),
         (T *)buf(m, gr.dst, 4), (const T *)m->slow[0], (const T *)m->slow[1],
         (const T *)m->slow[2], (const T *)m->slow[3], (const T *)m->slow[4],
         (const T *)m->slow[5], (const T *)m->slow[6]);
+}
+
+// --------------------------------------------------------------------------
+// lateral and upper damping (the relaxation of the paper's Listing 1): the
+// target of each prognostic is the boundary state interpolated in time,
+// mtratio (ref + bnd1) + tratio (ref + bnd2) - ref, and each value with a
+// nonzero rate relaxes implicitly, X <- (X + c X_target) / (1 + c),
+// c = dtau (nu_lat + nu_top).  Lanes whose levels all have rate 0 do no
+// memory traffic beyond the rates.
+// --------------------------------------------------------------------------
+template <typename T, class Lay, int L, bool TR>
+__device__ __forceinline__ void damp_body(const Lane<Lay, L> &ln, const MemberDev *m, int b,
+                                          double t, double dtau)
+{
+    const double nl = m->nu_lat[(size_t)ln.j * ln.nx + ln.i];
+    double nu[L];
+    bool any = false;
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        nu[l] = nl + m->nu_top[ln.k0 + l];
+        any = any || nu[l] != 0.0;
+    }
+    if (!any) return;
+    double tr = (t - m->t1) / (m->t2 - m->t1);
+    tr = tr < 0.0 ? 0.0 : (tr > 1.0 ? 1.0 : tr);
+    const T trt = (T)tr, mtt = (T)(1.0 - tr);
+    T cf[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) cf[l] = (T)(dtau * nu[l]);
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+        T x[L], b1[L], b2[L], ref[L];
+        T *xp = (T *)buf(m, b, f);
+        ln.load(xp, 0, 0, x);
+        ln.template load<true>((const T *)m->bnd[0][f], 0, 0, b1);
+        ln.template load<true>((const T *)m->bnd[1][f], 0, 0, b2);
+#pragma unroll
+        for (int l = 0; l < L; ++l) ref[l] = T(0);
+        if (f == 0 || f == 4) {
+            if constexpr (TR) ln.template load<true>((const T *)m->ref[f == 0 ? 0 : 1], 0, 0, ref);
+            else ln.vmet(m->vm, f == 0 ? VM_RHO : VM_RT, ref);
+        }
+        T out[L];
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            const T tgt = mtt * (ref[l] + b1[l]) + trt * (ref[l] + b2[l]) - ref[l];
+            const T y = (x[l] + cf[l] * tgt) / (T(1) + cf[l]);
+            const bool keep = nu[l] == 0.0 || (f == 3 && ln.k0 + l == 0);
+            out[l] = keep ? x[l] : y;
+        }
+        ln.store(xp, out);
+    }
+}
+
+template <typename T, class Lay, int L, bool TR>
+__global__ __launch_bounds__(BLOCK) void k_damp(Group gr, double offset, double frac)
+{
+    const Where wh = locate(gr);
+    if (!wh.active) return;
+    const MemberDev *m = wh.m;
+    if (!m->nu_lat) return;
+    const Lane<Lay, L> ln(m->nx, m->ny, m->nz, wh.i, wh.j);
+    damp_body<T, Lay, L, TR>(ln, m, gr.src, m->sums[2] + offset * m->dt, frac * m->dt);
+}
+
+__global__ void k_clock(Group gr)
+{
+    const int q = (int)threadIdx.x;
+    if (q >= gr.nm) return;
+    const MemberDev *m = gr.mem + (gr.nm == 1 ? gr.first : gr.ids[q]);
+    m->sums[2] = m->sums[2] + m->dt;
 }
 
 // --------------------------------------------------------------------------
@@ -1165,6 +1283,50 @@ __global__ __launch_bounds__(BLOCK) void k_sum_final(Group gr, int slot)
 }
 
 // --------------------------------------------------------------------------
+// seven-point diffusion (the bandwidth-model stencil): one read of each
+// value and one write per cell with perfect reuse, 7 reads + 1 write without
+// any; horizontal neighbours come through the caches, vertical ones by
+// segment shuffles.
+// --------------------------------------------------------------------------
+template <typename T, class Lay, int L>
+__device__ __forceinline__ void diffuse_body(const Lane<Lay, L> &ln, T kx, T ky, T kz,
+                                             const T *__restrict__ q, T *__restrict__ out)
+{
+    T c[L], w[L], e[L], s[L], n[L];
+    ln.load(q, 0, 0, c);
+    ln.load(q, -1, 0, w);
+    ln.load(q, 1, 0, e);
+    ln.load(q, 0, -1, s);
+    ln.load(q, 0, 1, n);
+    const T below = from_below(c[L - 1]), above = from_above(c[0]);
+    T r[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        const int k = ln.k0 + l;
+        const T qd = (l > 0) ? c[l - 1] : (k > 0 ? below : c[l]);
+        const T qu = (l < L - 1) ? c[l + 1] : (k < ln.nz - 1 ? above : c[l]);
+        const T lx = (w[l] + e[l]) - T(2) * c[l];
+        const T ly = (s[l] + n[l]) - T(2) * c[l];
+        const T lz = (qd + qu) - T(2) * c[l];
+        r[l] = c[l] + ((kx * lx + ky * ly) + kz * lz);
+    }
+    ln.store(out, r);
+}
+
+template <typename T, class Lay, int L>
+__global__ __launch_bounds__(BLOCK) void k_diffuse(DiffArgs a)
+{
+    const int ti = 1 << a.ti_log2, tj = kColsPerBlock >> a.ti_log2;
+    const int tiles_x = (a.nx + ti - 1) / ti;
+    const int t = (int)blockIdx.x, c = (int)threadIdx.x / SEG;
+    const int i = (t % tiles_x) * ti + (c & (ti - 1));
+    const int j = (t / tiles_x) * tj + (c >> a.ti_log2);
+    if (i >= a.nx || j >= a.ny) return;
+    const Lane<Lay, L> ln(a.nx, a.ny, a.nz, i, j);
+    diffuse_body<T, Lay, L>(ln, (T)a.kx, (T)a.ky, (T)a.kz, (const T *)a.in, (T *)a.out);
+}
+
+// --------------------------------------------------------------------------
 // dispatch
 // --------------------------------------------------------------------------
 template <template <typename, typename, class, int> class F, typename... Args>
@@ -1217,14 +1379,22 @@ struct RunFlux {
 
 template <typename T, typename S, class Lay, int L>
 struct RunShort {
+    template <bool TR, bool EV>
+    static void go(const Group &gr, double frac, hipStream_t s)
+    {
+        hipLaunchKernelGGL((k_short_step<T, S, Lay, L, TR, EV>), dim3(gr.nblocks), dim3(BLOCK), 0, s,
+                           gr, frac);
+    }
     static hipError_t run(const Group &gr, double frac, hipStream_t s)
     {
-        if (gr.terrain)
-            hipLaunchKernelGGL((k_short_step<T, S, Lay, L, true>), dim3(gr.nblocks), dim3(BLOCK), 0,
-                               s, gr, frac);
-        else
-            hipLaunchKernelGGL((k_short_step<T, S, Lay, L, false>), dim3(gr.nblocks), dim3(BLOCK), 0,
-                               s, gr, frac);
+        const bool ev = gr.ev != gr.src;
+        if (gr.terrain) {
+            if (ev) go<true, true>(gr, frac, s);
+            else go<true, false>(gr, frac, s);
+        } else {
+            if (ev) go<false, true>(gr, frac, s);
+            else go<false, false>(gr, frac, s);
+        }
         return hipGetLastError();
     }
 };
@@ -1268,6 +1438,48 @@ hipError_t launch_short_step(int prec, int layout, int L, const Group &gr, doubl
 hipError_t launch_sums(int prec, int layout, int L, const Group &gr, bool energy, hipStream_t s)
 {
     return dispatch<RunSums>(prec, layout, L, gr, energy, s);
+}
+
+template <typename T, typename S, class Lay, int L>
+struct RunDamp {
+    static hipError_t run(const Group &gr, double offset, double frac, hipStream_t s)
+    {
+        if (gr.terrain)
+            hipLaunchKernelGGL((k_damp<T, Lay, L, true>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr,
+                               offset, frac);
+        else
+            hipLaunchKernelGGL((k_damp<T, Lay, L, false>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr,
+                               offset, frac);
+        return hipGetLastError();
+    }
+};
+
+hipError_t launch_damp(int prec, int layout, int L, const Group &gr, double offset, double frac,
+                       hipStream_t s)
+{
+    return dispatch<RunDamp>(prec, layout, L, gr, offset, frac, s);
+}
+
+hipError_t launch_clock(const Group &gr, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_clock, dim3(1), dim3(256), 0, s, gr);
+    return hipGetLastError();
+}
+
+template <typename T, typename S, class Lay, int L>
+struct RunDiffuse {
+    static hipError_t run(const DiffArgs &a, hipStream_t s)
+    {
+        const int blocks = tiles_of(a.nx, a.ny, a.ti_log2);
+        hipLaunchKernelGGL((k_diffuse<T, Lay, L>), dim3(blocks), dim3(BLOCK), 0, s, a);
+        return hipGetLastError();
+    }
+};
+
+hipError_t launch_diffuse(int prec, int layout, int L, const DiffArgs &a, hipStream_t s)
+{
+    if (prec == 2) return hipErrorInvalidValue;   // no mixed form
+    return dispatch<RunDiffuse>(prec, layout, L, a, s);
 }
 
 }  // namespace hv

@@ -6,7 +6,8 @@
 // with the same nz, the member ids and a per-block (member, tile) map each
 // grouped launch uses; a single member's record travels in the kernel
 // arguments instead.  One long step is the launch sequence
-//   for each stage: slow prep, slow flux, n short steps   (per group)
+//   for each stage: slow prep, slow flux, n short steps   (per group;
+//                   two launches per short step in the Runge-Kutta form)
 //   mass partials + final sums                             (per group)
 // over three state buffers whose roles (start state, two running buffers)
 // rotate from one long step to the next; the roles cycle with period 2 or 3,
@@ -42,6 +43,8 @@ enum { KIND_PREP = 0, KIND_FLUX = 1, KIND_SHORT = 2, NKIND = 3 };
 
 struct MemberHost {
     int nx = 0, ny = 0, nz = 0, L = 0;
+    bool damp_room = false;    // workspace holds damping data
+    double *d_nu = nullptr;    // device: nu_lat (nx*ny) then nu_top (nz)
     double dx = 0, dy = 0, beta = 0.55, dt = -1.0;
     std::vector<double> zf;
     std::vector<double> h;     // surface heights (terrain), empty when flat
@@ -54,6 +57,7 @@ struct MemberHost {
 struct GroupHost {
     int L = 0;
     bool terrain = false;
+    bool damping = false;      // some member has damping data
     std::vector<int> ids;
     int *d_ids = nullptr;
     unsigned *d_blk[3] = {};   // per tile shape: block -> slot << 24 | tile (nm > 1)
@@ -72,6 +76,7 @@ struct GraphEntry {
 
 struct hv_ens {
     int n = 0, prec = 0, layout = 1;
+    bool rk2 = false;                // two-stage Runge-Kutta short steps
     size_t esize = 8;
     hipStream_t stream = nullptr;    // caller's stream
     hipStream_t own = nullptr;       // private stream for graph replay
@@ -133,6 +138,8 @@ std::string check_desc(const hv_grid_desc *d)
     if (d->precision < HV_FP64 || d->precision > HV_MIXED) return "unknown precision";
     if (d->layout != HV_IJK && d->layout != HV_KIJ) return "unknown layout";
     if (!(d->beta >= 0.5 && d->beta <= 1.0)) return "beta must be in [0.5, 1]";
+    if (d->short_scheme != HV_SHORT_FB && d->short_scheme != HV_SHORT_RK2) return "unknown short_scheme";
+    if (d->damping != 0 && d->damping != 1) return "damping must be 0 or 1";
     if (d->terrain) {
         const double H = d->zeta_faces[d->nz];
         const size_t nxy = (size_t)d->nx * d->ny;
@@ -206,6 +213,12 @@ Plan make_plan(int n, const hv_grid_desc *d)
         const size_t ncell = (size_t)d[q].nx * d[q].ny * d[q].nz;
         const size_t start = c.take(0);
         for (int a = 0; a < 25; ++a) c.take(ncell * es);
+        if (d[q].short_scheme == HV_SHORT_RK2)
+            for (int a = 0; a < 5; ++a) c.take(ncell * es);   // first-stage state
+        if (d[q].damping) {
+            for (int a = 0; a < 10; ++a) c.take(ncell * es);  // two boundary states
+            c.take(sizeof(double) * ((size_t)d[q].nx * d[q].ny + d[q].nz));
+        }
         if (d[q].terrain) {
             // Omega, three reference fields, per-column geometry
             for (int a = 0; a < 4; ++a) c.take(ncell * es);
@@ -307,8 +320,10 @@ void fill_geo(const MemberHost &m, std::vector<double> &geo)
 
 hipError_t sync(hv_ens *e) { return hipStreamSynchronize(e->stream); }
 
-// Launch description of group g for a kernel kind (< 0: the sums).
-hv::Group group_launch(const hv_ens *e, const GroupHost &g, int kind, int src, int dst = 0)
+// Launch description of group g for a kernel kind (< 0: the sums); ev < 0
+// means the short step takes its explicit terms from src.
+hv::Group group_launch(const hv_ens *e, const GroupHost &g, int kind, int src, int dst = 0,
+                       int ev = -1)
 {
     hv::Group gr{};
     gr.mem = e->d_mem;
@@ -316,6 +331,7 @@ hv::Group group_launch(const hv_ens *e, const GroupHost &g, int kind, int src, i
     gr.nm = (int)g.ids.size();
     gr.src = src;
     gr.dst = dst;
+    gr.ev = ev < 0 ? src : ev;
     gr.terrain = g.terrain ? 1 : 0;
     if (kind < 0) {
         gr.blk = g.d_pblk;
@@ -391,12 +407,34 @@ hipError_t enqueue_long_step(hv_ens *e, int n_short, const int r[3], hipStream_t
         }
         for (int q = 0; q < n_short; ++q) {
             const int src = q == 0 ? P : R[(q - 1) & 1], dst = R[q & 1];
+            const double f = frac[st] / n_short;
             for (auto &g : e->groups) {
-                const hv::Group gs = group_launch(e, g, KIND_SHORT, src, dst);
-                err = traced(e, s, HV_K_SHORT_STEP, [&] {
-                    return hv::launch_short_step(e->prec, e->layout, g.L, gs, frac[st] / n_short, s);
-                });
+                const hv::Group gd = group_launch(e, g, KIND_SHORT, dst);
+                if (e->rk2) {
+                    // X* = Phi(X, X, dtau/2) into buffer 3, then X+ = Phi(X, X*, dtau)
+                    const hv::Group g1 = group_launch(e, g, KIND_SHORT, src, 3);
+                    err = traced(e, s, HV_K_SHORT_STEP, [&] {
+                        return hv::launch_short_step(e->prec, e->layout, g.L, g1, 0.5 * f, s);
+                    });
+                    if (err != hipSuccess) return err;
+                    const hv::Group g2 = group_launch(e, g, KIND_SHORT, src, dst, 3);
+                    err = traced(e, s, HV_K_SHORT_STEP, [&] {
+                        return hv::launch_short_step(e->prec, e->layout, g.L, g2, f, s);
+                    });
+                } else {
+                    const hv::Group gs = group_launch(e, g, KIND_SHORT, src, dst);
+                    err = traced(e, s, HV_K_SHORT_STEP, [&] {
+                        return hv::launch_short_step(e->prec, e->layout, g.L, gs, f, s);
+                    });
+                }
                 if (err != hipSuccess) return err;
+                if (g.damping) {
+                    // at the end of this short step: t_n + (q + 1) dtau
+                    err = traced(e, s, HV_K_DAMP, [&] {
+                        return hv::launch_damp(e->prec, e->layout, g.L, gd, (q + 1) * f, f, s);
+                    });
+                    if (err != hipSuccess) return err;
+                }
             }
         }
     }
@@ -405,6 +443,7 @@ hipError_t enqueue_long_step(hv_ens *e, int n_short, const int r[3], hipStream_t
         const hv::Group gm = group_launch(e, g, -1, cur);
         err = traced(e, s, HV_K_MASS, [&] { return hv::launch_sums(e->prec, e->layout, g.L, gm, false, s); });
         if (err != hipSuccess) return err;
+        if (g.damping && (err = hv::launch_clock(gm, s)) != hipSuccess) return err;
     }
     return hipSuccess;
 }
@@ -484,8 +523,9 @@ int ens_create(hv_ens *e, int n, const hv_grid_desc *descs, void *ws, size_t byt
     for (int q = 0; q < n; ++q) {
         std::string why = check_desc(&descs[q]);
         if (!why.empty()) return fail(nullptr, HV_ERR_ARG, (n > 1 ? "member " + std::to_string(q) + ": " : "") + why);
-        if (descs[q].precision != descs[0].precision || descs[q].layout != descs[0].layout)
-            return fail(nullptr, HV_ERR_ARG, "all members must share precision and layout");
+        if (descs[q].precision != descs[0].precision || descs[q].layout != descs[0].layout ||
+            descs[q].short_scheme != descs[0].short_scheme)
+            return fail(nullptr, HV_ERR_ARG, "all members must share precision, layout and short_scheme");
         if (unsupported(&descs[q], &why)) return fail(nullptr, HV_ERR_UNSUPPORTED, why);
     }
     const Plan p = make_plan(n, descs);
@@ -500,6 +540,7 @@ int ens_create(hv_ens *e, int n, const hv_grid_desc *descs, void *ws, size_t byt
     e->n = n;
     e->prec = descs[0].precision;
     e->layout = descs[0].layout;
+    e->rk2 = descs[0].short_scheme == HV_SHORT_RK2;
     e->esize = elem_size(e->prec);
     e->stream = (hipStream_t)stream;
     e->d_mem = (hv::MemberDev *)(base + p.table);
@@ -519,11 +560,23 @@ int ens_create(hv_ens *e, int n, const hv_grid_desc *descs, void *ws, size_t byt
         v.rdx = 1.0 / m.dx; v.rdy = 1.0 / m.dy; v.beta = m.beta; v.dt = 0.0;
         for (int b = 0; b < 3; ++b)
             for (int f = 0; f < 5; ++f) v.st[b][f] = base + c.take(m.ncell * e->esize);
+        for (int f = 0; f < 5; ++f) v.st[3][f] = e->rk2 ? base + c.take(m.ncell * e->esize) : nullptr;
         for (int f = 0; f < 7; ++f) v.slow[f] = base + c.take(m.ncell * e->esize);
         for (int f = 0; f < 3; ++f) v.spec[f] = base + c.take(m.ncell * e->esize);
         v.spec[3] = nullptr;
         v.geo = nullptr;
         v.ref[0] = v.ref[1] = v.ref[2] = nullptr;
+        v.nu_lat = v.nu_top = nullptr;
+        v.t1 = 0.0;
+        v.t2 = 1.0;
+        for (int b = 0; b < 2; ++b)
+            for (int f = 0; f < 5; ++f) v.bnd[b][f] = nullptr;
+        if (d.damping) {
+            m.damp_room = true;
+            for (int b = 0; b < 2; ++b)
+                for (int f = 0; f < 5; ++f) v.bnd[b][f] = base + c.take(m.ncell * e->esize);
+            m.d_nu = (double *)(base + c.take(sizeof(double) * ((size_t)m.nx * m.ny + m.nz)));
+        }
         if (d.terrain) {
             m.h.assign(d.terrain, d.terrain + (size_t)d.nx * d.ny);
             v.spec[3] = base + c.take(m.ncell * e->esize);
@@ -659,6 +712,9 @@ int member_init(hv_ens *e, int q, const double *const fields[5], const double *r
             add(rho_ref[(size_t)k * nxy + col] * vol * (1.0 - m.h[col] / H));
     }
     m.mass_ref = s + c;
+    const double zero = 0.0;   // model time
+    if ((r = hipMemcpy(m.dev.sums + 2, &zero, sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, r, "hipMemcpy(time)");
     m.have_state = true;
     for (auto &g : e->groups) {
         const hv::Group gm = group_launch(e, g, -1, e->roles[0]);
@@ -783,6 +839,73 @@ int member_mass(hv_ens *e, int q, double *mass, double *energy)
     if (mass) *mass = ms;
     if (energy) *energy = h[1];
     if (!std::isfinite(ms)) return fail(e, HV_ERR_NONFINITE, "mass sum is not finite");
+    return HV_OK;
+}
+
+hipError_t upload_table(hv_ens *e)
+{
+    std::vector<hv::MemberDev> table(e->n);
+    for (int q = 0; q < e->n; ++q) table[q] = e->m[q].dev;
+    return hipMemcpy(e->d_mem, table.data(), sizeof(hv::MemberDev) * e->n, hipMemcpyHostToDevice);
+}
+
+int member_damping(hv_ens *e, int q, const double *nu_lat, const double *nu_top,
+                   const double *const bnd1[5], const double *const bnd2[5], double t1, double t2,
+                   double time_now)
+{
+    if (q < 0 || q >= e->n) return fail(e, HV_ERR_ARG, "member index out of range");
+    MemberHost &m = e->m[q];
+    if (!m.damp_room) return fail(e, HV_ERR_ARG, "workspace has no room for damping (desc.damping = 0)");
+    if (!nu_lat || !nu_top || !bnd1 || !bnd2) return fail(e, HV_ERR_ARG, "NULL damping array");
+    if (!(t2 > t1) || !std::isfinite(t1) || !std::isfinite(t2) || !std::isfinite(time_now))
+        return fail(e, HV_ERR_ARG, "need finite t1 < t2 and time_now");
+    const size_t nxy = (size_t)m.nx * m.ny;
+    for (size_t c = 0; c < nxy; ++c)
+        if (!(nu_lat[c] >= 0.0) || !std::isfinite(nu_lat[c])) return fail(e, HV_ERR_ARG, "rates must be finite and >= 0");
+    for (int k = 0; k < m.nz; ++k)
+        if (!(nu_top[k] >= 0.0) || !std::isfinite(nu_top[k])) return fail(e, HV_ERR_ARG, "rates must be finite and >= 0");
+    for (int b = 0; b < 2; ++b) {
+        const double *const *bs = b ? bnd2 : bnd1;
+        for (int f = 0; f < 5; ++f) {
+            if (!bs[f]) return fail(e, HV_ERR_ARG, "NULL boundary field");
+            const size_t cnt = f == HV_RHOW ? nxy * (m.nz + 1) : nxy * m.nz;
+            for (size_t c = 0; c < cnt; ++c)
+                if (!std::isfinite(bs[f][c])) return fail(e, HV_ERR_ARG, "non-finite boundary value");
+        }
+        for (size_t c = 0; c < nxy; ++c)
+            if (bs[HV_RHOW][c] != 0.0 || bs[HV_RHOW][nxy * m.nz + c] != 0.0)
+                return fail(e, HV_ERR_ARG, "boundary rho*w must be 0 on both lids");
+    }
+    hipError_t r = sync(e);
+    if (r != hipSuccess) return hip_fail(e, r, "stream synchronize");
+    std::vector<double> nu(nxy + m.nz);
+    std::copy(nu_lat, nu_lat + nxy, nu.begin());
+    std::copy(nu_top, nu_top + m.nz, nu.begin() + nxy);
+    if ((r = hipMemcpy(m.d_nu, nu.data(), nu.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, r, "hipMemcpy(rates)");
+    std::vector<double> bd;
+    std::vector<float> bf;
+    if (e->prec == HV_FP64) bd.resize(m.ncell);
+    else bf.resize(m.ncell);
+    for (int b = 0; b < 2; ++b)
+        for (int f = 0; f < 5; ++f) {
+            const double *src = (b ? bnd2 : bnd1)[f];
+            const void *h;
+            if (e->prec == HV_FP64) { to_device_order(e->layout, m, src, bd.data()); h = bd.data(); }
+            else { to_device_order(e->layout, m, src, bf.data()); h = bf.data(); }
+            if ((r = hipMemcpy(m.dev.bnd[b][f], h, m.ncell * e->esize, hipMemcpyHostToDevice)) != hipSuccess)
+                return hip_fail(e, r, "hipMemcpy(boundary)");
+        }
+    if ((r = hipMemcpy(m.dev.sums + 2, &time_now, sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, r, "hipMemcpy(time)");
+    m.dev.nu_lat = m.d_nu;
+    m.dev.nu_top = m.d_nu + nxy;
+    m.dev.t1 = t1;
+    m.dev.t2 = t2;
+    if ((r = upload_table(e)) != hipSuccess) return hip_fail(e, r, "upload member table");
+    for (auto &g : e->groups)
+        if (std::find(g.ids.begin(), g.ids.end(), q) != g.ids.end()) g.damping = true;
+    drop_graphs(e);
     return HV_OK;
 }
 
@@ -920,6 +1043,14 @@ int hv_tune(hv_grid_t g, int32_t *tile_x_out)
     return tune(g, tile_x_out, nullptr);
 }
 
+int hv_damping(hv_grid_t g, const double *nu_lat, const double *nu_top,
+               const double *const bnd1[5], const double *const bnd2[5], double t1, double t2,
+               double time_now)
+{
+    if (!g) return fail(nullptr, HV_ERR_ARG, "handle is NULL");
+    return member_damping(g, 0, nu_lat, nu_top, bnd1, bnd2, t1, t2, time_now);
+}
+
 int hv_trace(hv_grid_t g, int32_t on)
 {
     if (!g) return fail(nullptr, HV_ERR_ARG, "handle is NULL");
@@ -943,8 +1074,9 @@ size_t hv_ens_workspace_bytes(int32_t n, const hv_grid_desc *descs)
     for (int q = 0; q < n; ++q) {
         std::string why = check_desc(&descs[q]);
         if (!why.empty()) { g_global_error = (n > 1 ? "member " + std::to_string(q) + ": " : "") + why; return 0; }
-        if (descs[q].precision != descs[0].precision || descs[q].layout != descs[0].layout) {
-            g_global_error = "all members must share precision and layout";
+        if (descs[q].precision != descs[0].precision || descs[q].layout != descs[0].layout ||
+            descs[q].short_scheme != descs[0].short_scheme) {
+            g_global_error = "all members must share precision, layout and short_scheme";
             return 0;
         }
     }
@@ -996,6 +1128,14 @@ int hv_ens_tune(hv_ens_t e, int32_t *tile_x_out, int32_t *ngroups_out)
     return tune(e, tile_x_out, ngroups_out);
 }
 
+int hv_ens_damping(hv_ens_t e, int32_t member, const double *nu_lat, const double *nu_top,
+                   const double *const bnd1[5], const double *const bnd2[5], double t1, double t2,
+                   double time_now)
+{
+    if (!e) return fail(nullptr, HV_ERR_ARG, "handle is NULL");
+    return member_damping(e, member, nu_lat, nu_top, bnd1, bnd2, t1, t2, time_now);
+}
+
 int hv_ens_trace(hv_ens_t e, int32_t on)
 {
     if (!e) return fail(nullptr, HV_ERR_ARG, "handle is NULL");
@@ -1009,6 +1149,37 @@ int hv_ens_trace_read(hv_ens_t e, int32_t kind, double *ms_total, int64_t *launc
 }
 
 void hv_ens_destroy(hv_ens_t e) { delete e; }
+
+// ------------------------------------------------------- 7-point stencil ---
+int hv_diffuse(int32_t nx, int32_t ny, int32_t nz, int32_t precision, int32_t layout, double kx,
+               double ky, double kz, int32_t tile_x, const void *dev_in, void *dev_out,
+               void *hip_stream)
+{
+    if (nx < 1 || ny < 1) return fail(nullptr, HV_ERR_ARG, "nx and ny must be >= 1");
+    if (nz != 32 && nz != 64 && nz != 128) return fail(nullptr, HV_ERR_ARG, "nz must be 32, 64 or 128");
+    if ((size_t)nx * (size_t)ny > (size_t)INT32_MAX / 2) return fail(nullptr, HV_ERR_ARG, "too many columns");
+    if (precision != HV_FP64 && precision != HV_FP32)
+        return fail(nullptr, HV_ERR_ARG, "precision must be HV_FP64 or HV_FP32");
+    if (layout != HV_IJK && layout != HV_KIJ) return fail(nullptr, HV_ERR_ARG, "unknown layout");
+    if (!std::isfinite(kx) || !std::isfinite(ky) || !std::isfinite(kz))
+        return fail(nullptr, HV_ERR_ARG, "coefficients must be finite");
+    if (!dev_in || !dev_out) return fail(nullptr, HV_ERR_ARG, "NULL device array");
+    if (dev_in == dev_out) return fail(nullptr, HV_ERR_ARG, "dev_in and dev_out must differ");
+    if (((uintptr_t)dev_in | (uintptr_t)dev_out) % 64)
+        return fail(nullptr, HV_ERR_ARG, "device arrays must be 64-byte aligned");
+    int tl = -1;
+    for (int sh = 0; sh < 3; ++sh)
+        if (tile_x == (1 << kShapes[sh])) tl = kShapes[sh];
+    if (tl < 0) return fail(nullptr, HV_ERR_ARG, "tile_x must be 16, 8 or 4");
+    hv::DiffArgs a{};
+    a.nx = nx; a.ny = ny; a.nz = nz; a.ti_log2 = tl;
+    a.kx = kx; a.ky = ky; a.kz = kz;
+    a.in = dev_in; a.out = dev_out;
+    const hipError_t r = hv::launch_diffuse(precision == HV_FP64 ? 0 : 1, layout, nz / hv::kSeg, a,
+                                            (hipStream_t)hip_stream);
+    if (r != hipSuccess) return hip_fail(nullptr, r, "diffuse launch");
+    return HV_OK;
+}
 
 const char *hv_ens_last_error(hv_ens_t e) { return e ? e->err.c_str() : g_global_error.c_str(); }
 

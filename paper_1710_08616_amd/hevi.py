@@ -23,15 +23,17 @@ RHO_PTB, RHOU, RHOV, RHOW, RHOTHETA_PTB = 0, 1, 2, 3, 4
 
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "mixed": MIXED}
 LAYOUTS = {"ijk": IJK, "kij": KIJ}
+SHORT_FB, SHORT_RK2 = 0, 1
+SHORT_SCHEMES = {"fb": SHORT_FB, "rk2": SHORT_RK2}
 
 EXPORTS = ("hv_workspace_bytes", "hv_grid_create", "hv_state_init", "hv_step", "hv_state_read",
            "hv_mass", "hv_tune", "hv_trace", "hv_trace_read", "hv_grid_destroy", "hv_last_error",
            "hv_ens_workspace_bytes", "hv_ens_create", "hv_ens_state_init", "hv_ens_step",
            "hv_ens_state_read", "hv_ens_mass", "hv_ens_tune", "hv_ens_trace", "hv_ens_trace_read",
-           "hv_ens_destroy", "hv_ens_last_error")
-K_SLOW_PREP, K_SLOW_FLUX, K_SHORT_STEP, K_MASS = 0, 1, 2, 3
+           "hv_ens_destroy", "hv_ens_last_error", "hv_diffuse", "hv_damping", "hv_ens_damping")
+K_SLOW_PREP, K_SLOW_FLUX, K_SHORT_STEP, K_MASS, K_DAMP = 0, 1, 2, 3, 4
 KERNEL_KINDS = {"slow_prep": K_SLOW_PREP, "slow_flux": K_SLOW_FLUX, "short_step": K_SHORT_STEP,
-                "mass": K_MASS}
+                "mass": K_MASS, "damp": K_DAMP}
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -47,7 +49,8 @@ class GridDesc(ctypes.Structure):
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double),
                 ("zeta_faces", _dp), ("terrain", _dp),
                 ("precision", ctypes.c_int32), ("layout", ctypes.c_int32),
-                ("beta", ctypes.c_double), ("div_damp", ctypes.c_double)]
+                ("beta", ctypes.c_double), ("div_damp", ctypes.c_double),
+                ("short_scheme", ctypes.c_int32), ("damping", ctypes.c_int32)]
 
 
 _lib = None
@@ -108,6 +111,16 @@ def load():
     L.hv_ens_destroy.argtypes = [ctypes.c_void_p]
     L.hv_ens_last_error.restype = ctypes.c_char_p
     L.hv_ens_last_error.argtypes = [ctypes.c_void_p]
+    L.hv_damping.restype = ctypes.c_int
+    L.hv_damping.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.POINTER(_dp), ctypes.POINTER(_dp),
+                             ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    L.hv_ens_damping.restype = ctypes.c_int
+    L.hv_ens_damping.argtypes = [ctypes.c_void_p, ctypes.c_int32, _dp, _dp, ctypes.POINTER(_dp),
+                                 ctypes.POINTER(_dp), ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double]
+    L.hv_diffuse.restype = ctypes.c_int
+    L.hv_diffuse.argtypes = [ctypes.c_int32] * 5 + [ctypes.c_double] * 3 + [
+        ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     L.hv_grid_destroy.restype = None
     L.hv_grid_destroy.argtypes = [ctypes.c_void_p]
     L.hv_last_error.restype = ctypes.c_char_p
@@ -116,9 +129,12 @@ def load():
     return L
 
 
-def make_desc(nx, ny, nz, dx, dy, zf, precision="fp32", layout="kij", beta=0.55, terrain=None):
+def make_desc(nx, ny, nz, dx, dy, zf, precision="fp32", layout="kij", beta=0.55, terrain=None,
+              short="fb", damping=False):
     """A filled hv_grid_desc plus the arrays it points into (keep them alive
-    until the grid is created).  terrain: (ny, nx) surface heights or None."""
+    until the grid is created).  terrain: (ny, nx) surface heights or None;
+    short: "fb" (forward-backward) or "rk2" (two-stage Runge-Kutta) short step;
+    damping: reserve workspace for lateral / upper damping data."""
     zf = np.ascontiguousarray(zf, dtype=np.float64)
     keep = [zf]
     tp = None
@@ -132,8 +148,22 @@ def make_desc(nx, ny, nz, dx, dy, zf, precision="fp32", layout="kij", beta=0.55,
                  zf.ctypes.data_as(_dp), tp,
                  PRECISIONS[precision] if isinstance(precision, str) else int(precision),
                  LAYOUTS[layout] if isinstance(layout, str) else int(layout),
-                 float(beta), 0.0)
+                 float(beta), 0.0, SHORT_SCHEMES[short] if isinstance(short, str) else int(short),
+                 1 if damping else 0)
     return d, keep
+
+
+def _damping_args(d):
+    """Marshal a damping dict (nu_lat, nu_top, bnd1, bnd2, t1, t2) for the ABI."""
+    keep = [np.ascontiguousarray(d["nu_lat"], dtype=np.float64),
+            np.ascontiguousarray(d["nu_top"], dtype=np.float64)]
+    b1 = [np.ascontiguousarray(x, dtype=np.float64) for x in d["bnd1"]]
+    b2 = [np.ascontiguousarray(x, dtype=np.float64) for x in d["bnd2"]]
+    keep += b1 + b2
+    p1 = (_dp * 5)(*[x.ctypes.data_as(_dp) for x in b1])
+    p2 = (_dp * 5)(*[x.ctypes.data_as(_dp) for x in b2])
+    return keep, [keep[0].ctypes.data_as(_dp), keep[1].ctypes.data_as(_dp), p1, p2,
+                  float(d["t1"]), float(d["t2"])]
 
 
 def workspace_bytes(desc: GridDesc) -> int:
@@ -154,14 +184,15 @@ class Domain:
     """
 
     def __init__(self, state, precision="fp32", layout="kij", device="cuda", stream=None,
-                 init=True):
+                 init=True, short="fb"):
         import torch
         self._torch = torch
         L = load()
         self.nx, self.ny, self.nz = int(state.nx), int(state.ny), int(state.nz)
+        dmp = getattr(state, "damping", None)
         self.desc, self._keep = make_desc(state.nx, state.ny, state.nz, state.dx, state.dy,
                                           state.zf, precision, layout, getattr(state, "beta", 0.55),
-                                          getattr(state, "terrain", None))
+                                          getattr(state, "terrain", None), short, dmp is not None)
         nbytes = workspace_bytes(self.desc)
         if nbytes == 0:
             raise HvError(HV_ERR_ARG, last_error())
@@ -175,8 +206,15 @@ class Domain:
         self.handle = h
         if init:
             self.init(state.fields, state.rho_ref, state.rt_ref, state.p_ref)
+            if dmp is not None:
+                self.set_damping(dmp)
 
     # -- ABI wrappers -------------------------------------------------------
+    def set_damping(self, d, time_now: float = 0.0):
+        """hv_damping with a dict of nu_lat, nu_top, bnd1, bnd2, t1, t2."""
+        keep, args = _damping_args(d)
+        return self._check(load().hv_damping(self.handle, *args, float(time_now)))
+
     def _check(self, rc):
         if rc != HV_OK:
             raise HvError(rc, last_error(self.handle))
@@ -253,7 +291,7 @@ class Ensemble:
     """
 
     def __init__(self, states, precision="fp32", layout="kij", device="cuda", stream=None,
-                 init=True):
+                 init=True, short="fb"):
         import torch
         L = load()
         self.n = len(states)
@@ -262,7 +300,8 @@ class Ensemble:
         descs = (GridDesc * self.n)()
         for q, s in enumerate(states):
             d, keep = make_desc(s.nx, s.ny, s.nz, s.dx, s.dy, s.zf, precision, layout,
-                                getattr(s, "beta", 0.55), getattr(s, "terrain", None))
+                                getattr(s, "beta", 0.55), getattr(s, "terrain", None), short,
+                                getattr(s, "damping", None) is not None)
             descs[q] = d
             self._keep.append(keep)
         self._descs = descs
@@ -281,6 +320,13 @@ class Ensemble:
         if init:
             for q, s in enumerate(states):
                 self.init(q, s.fields, s.rho_ref, s.rt_ref, s.p_ref)
+                if getattr(s, "damping", None) is not None:
+                    self.set_damping(q, s.damping)
+
+    def set_damping(self, member, d, time_now: float = 0.0):
+        keep, args = _damping_args(d)
+        return self._check(load().hv_ens_damping(self.handle, int(member), *args,
+                                                 float(time_now)))
 
     def _check(self, rc):
         if rc != HV_OK:
@@ -344,3 +390,30 @@ class Ensemble:
             self.close()
         except Exception:
             pass
+
+
+def diffuse(q_in, q_out, kx: float, ky: float, kz: float, layout="kij", tile_x: int = 16,
+            stream=None):
+    """One seven-point diffusion step (hv_diffuse) from device tensor q_in into
+    q_out (same shape and dtype, float32 or float64).  Shapes: (ny, nx, nz)
+    for the column-fastest layout, (nz, ny, nx) for the i-fastest one."""
+    import torch
+    if q_in.dtype != q_out.dtype or q_in.shape != q_out.shape:
+        raise ValueError("q_in and q_out must match")
+    if not (q_in.is_contiguous() and q_out.is_contiguous()):
+        raise ValueError("tensors must be contiguous")
+    lay = LAYOUTS[layout] if isinstance(layout, str) else int(layout)
+    if lay == KIJ:
+        ny, nx, nz = q_in.shape
+    else:
+        nz, ny, nx = q_in.shape
+    prec = {torch.float64: FP64, torch.float32: FP32}.get(q_in.dtype)
+    if prec is None:
+        raise ValueError("dtype must be float32 or float64")
+    s = stream if stream is not None else torch.cuda.current_stream(q_in.device)
+    rc = load().hv_diffuse(nx, ny, nz, prec, lay, float(kx), float(ky), float(kz), int(tile_x),
+                           ctypes.c_void_p(q_in.data_ptr()), ctypes.c_void_p(q_out.data_ptr()),
+                           ctypes.c_void_p(s.cuda_stream))
+    if rc != HV_OK:
+        raise HvError(rc, last_error())
+    return q_out

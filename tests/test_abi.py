@@ -103,6 +103,18 @@ def test_invalid_terrain_is_rejected_before_any_device_call(hv, bad):
                                     ctypes.byref(h)) == hv.HV_ERR_ARG
 
 
+def test_short_scheme_is_checked_and_sizes_the_workspace(hv):
+    d, _z = _desc(hv)
+    fb = hv.load().hv_workspace_bytes(ctypes.byref(d))
+    d.short_scheme = hv.SHORT_RK2
+    rk2 = hv.load().hv_workspace_bytes(ctypes.byref(d))
+    # one more state (5 fields) for the first-stage value
+    assert rk2 - fb >= 5 * 16 * 12 * d.nz * 4
+    d.short_scheme = 7
+    assert hv.load().hv_workspace_bytes(ctypes.byref(d)) == 0
+    assert "short_scheme" in hv.last_error()
+
+
 def test_terrain_adds_its_arrays_to_the_workspace(hv):
     d, _z = _desc(hv)
     flat = hv.load().hv_workspace_bytes(ctypes.byref(d))
@@ -122,3 +134,22 @@ def test_null_handle_calls_fail_cleanly(hv):
     assert L.hv_mass(None, None, None) == hv.HV_ERR_ARG
     L.hv_grid_destroy(None)
     assert "handle" in hv.last_error()
+
+
+def test_diffuse_rejects_bad_arguments_before_any_launch(hv):
+    L = hv.load()
+    a, b = ctypes.c_void_p(4096), ctypes.c_void_p(8192)
+    ok = dict(nx=8, ny=8, nz=32, p=hv.FP32, lay=hv.KIJ, t=16)
+
+    def call(nx=8, ny=8, nz=32, p=hv.FP32, lay=hv.KIJ, t=16, x=a, y=b, k=0.1):
+        return L.hv_diffuse(nx, ny, nz, p, lay, k, k, k, t, x, y, None)
+
+    assert call(nz=48) == hv.HV_ERR_ARG and "nz" in hv.last_error()
+    assert call(p=hv.MIXED) == hv.HV_ERR_ARG and "precision" in hv.last_error()
+    assert call(lay=5) == hv.HV_ERR_ARG
+    assert call(t=5) == hv.HV_ERR_ARG and "tile_x" in hv.last_error()
+    assert call(y=a) == hv.HV_ERR_ARG and "differ" in hv.last_error()
+    assert call(x=ctypes.c_void_p(4100)) == hv.HV_ERR_ARG and "aligned" in hv.last_error()
+    assert call(x=None) == hv.HV_ERR_ARG
+    assert call(k=float("nan")) == hv.HV_ERR_ARG
+    assert call(nx=0) == hv.HV_ERR_ARG

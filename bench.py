@@ -77,10 +77,17 @@ def read_traffic(prec: str):
     return None
 
 
-def time_precision(hevi, s, prec, steps, warmup, layout="kij", keep=False, short="fb"):
+def time_precision(hevi, s, prec, steps, warmup, layout="kij", keep=False, short="fb", tune=True):
     import torch
     log(f"[bench] {prec}: init {s.nx}x{s.ny}x{s.nz}")
     d = hevi.Domain(s, precision=prec, layout=layout, short=short)
+    tiles = None
+    if tune:
+        # the autotuner times each tile shape per kernel kind on this state
+        # (results are bitwise independent of the shape; the state is left
+        # unchanged)
+        tiles = d.tune()
+        log(f"[bench] {prec}: tiles (x-extent per kind) {tiles}")
     if warmup:
         d.step(s.dt, warmup, s.n_short)
     m0 = d.mass()
@@ -118,6 +125,7 @@ def time_precision(hevi, s, prec, steps, warmup, layout="kij", keep=False, short
         "kernels_ms_avg": {k: (v[0] / v[1] if v[1] else None) for k, v in kern.items()},
         "kernels_launches": {k: v[1] for k, v in kern.items()},
         "kernels_ms_total": {k: v[0] for k, v in kern.items()},
+        "tile_x": tiles,
     }
     log(f"[bench] {prec}: {res['ms_per_step']:.3f} ms/step (graph replay {res['graph_ms_per_step']:.3f}), "
         f"{res['cell_updates_per_s']:.3e} cell-updates/s, model {res['model_gbps']:.0f} GB/s")
@@ -285,6 +293,9 @@ def main():
     ap.add_argument("--workload", default="large")
     ap.add_argument("--short", default="fb", choices=["fb", "rk2"],
                     help="short-step integrator: forward-backward or two-stage Runge-Kutta")
+    ap.add_argument("--damping", action="store_true",
+                    help="lateral (8-cell) and upper (above 15 km) damping toward synthetic "
+                         "boundary data after every short step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--accuracy", action="store_true",
                     help="per-field error of every path against the float64 oracle on the "
@@ -366,6 +377,8 @@ def main():
 
     t0 = time.time()
     s = inputs.workload(args.workload)
+    if args.damping:
+        s.damping = inputs.damping(s)
     log(f"[bench] state {s.nx}x{s.ny}x{s.nz} generated in {time.time() - t0:.1f} s")
     precs = [p for p in args.precisions.split(",") if p]
     terrain = s.terrain is not None
@@ -422,7 +435,7 @@ def main():
                                f", dt=10 s, {s.n_short} short steps/stage",
                    "nx": s.nx, "ny": s.ny, "nz": s.nz, "n_short": s.n_short, "dt": s.dt,
                    "precision": primary, "layout": args.layout, "short_step": args.short,
-                   "parallelism": "1 GPU"},
+                   "damping": bool(args.damping), "parallelism": "1 GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "model_gbps": r["model_gbps"],

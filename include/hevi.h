@@ -217,8 +217,10 @@ int hv_ens_state_init(hv_ens_t e, int32_t member, const double *const fields[5],
 int hv_ens_step(hv_ens_t e, const double *dt_per_member, int32_t n_long, int32_t n_short);
 int hv_ens_state_read(hv_ens_t e, int32_t member, int32_t field, double *host_out);
 int hv_ens_mass(hv_ens_t e, int32_t member, double *mass_out, double *energy_out);
-/* As hv_tune, per group of members with equal nz (groups in increasing nz):
- * tile_x_out receives 3 entries per group, *ngroups_out the group count. */
+/* As hv_tune, per launch group: members with equal nz and terrain flag,
+ * flat groups first, each kind in increasing nz;
+ * tile_x_out receives 3 entries per group (room for 18: at most 6 groups),
+ * *ngroups_out the group count. */
 int hv_ens_tune(hv_ens_t e, int32_t *tile_x_out, int32_t *ngroups_out);
 int hv_ens_damping(hv_ens_t e, int32_t member, const double *nu_lat, const double *nu_top,
                    const double *const bnd1[5], const double *const bnd2[5], double t1, double t2,

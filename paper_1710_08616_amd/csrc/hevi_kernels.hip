@@ -58,6 +58,7 @@ struct Where {
     int i, j;
     bool active;
 };
+template <int SG = SEG>
 __device__ __forceinline__ Where locate(const Group &gr)
 {
     Where w;
@@ -70,7 +71,7 @@ __device__ __forceinline__ Where locate(const Group &gr)
     w.m = gr.mem + id;
     const int ti = 1 << gr.ti_log2, tj = kColsPerBlock >> gr.ti_log2;
     const int tiles_x = (w.m->nx + ti - 1) / ti;
-    const int c = (int)threadIdx.x / SEG;
+    const int c = (int)threadIdx.x / SG;
     w.i = (t % tiles_x) * ti + (c & (ti - 1));
     w.j = (t / tiles_x) * tj + (c >> gr.ti_log2);
     w.active = w.i < w.m->nx && w.j < w.m->ny;
@@ -96,7 +97,9 @@ struct IJK {
 // Field f of state buffer b.
 __device__ __forceinline__ void *buf(const MemberDev *m, int b, int f) { return m->st[b][f]; }
 
-template <class Lay, int L>
+// One lane's share of a column: segments of SG lanes per column (16, or 32
+// for the float64-solve short step), lane p owning levels p*L .. p*L+L-1.
+template <class Lay, int L, int SG = SEG>
 struct Lane {
     int i, j, p, k0, nx, ny, nz;
     size_t kstride;
@@ -106,7 +109,7 @@ struct Lane {
         nx = nx_; ny = ny_; nz = nz_;
         i = i_;
         j = j_;
-        p = threadIdx.x % SEG;
+        p = threadIdx.x % SG;
         k0 = p * L;
         kstride = Lay::kContig ? 1 : (size_t)nx * ny;
     }
@@ -169,9 +172,10 @@ struct Lane {
     }
 };
 
-// value of lane p-1 (lane 0 keeps its own) / of lane p+1 (lane 15 keeps its own)
-template <typename T> __device__ __forceinline__ T from_below(T x) { return __shfl_up(x, 1u, SEG); }
-template <typename T> __device__ __forceinline__ T from_above(T x) { return __shfl_down(x, 1u, SEG); }
+// value of lane p-1 (lane 0 keeps its own) / of lane p+1 (the segment's last
+// lane keeps its own), within segments of SG lanes
+template <int SG = SEG, typename T> __device__ __forceinline__ T from_below(T x) { return __shfl_up(x, 1u, SG); }
+template <int SG = SEG, typename T> __device__ __forceinline__ T from_above(T x) { return __shfl_down(x, 1u, SG); }
 
 // e[0..L+3] = levels k0-2 .. k0+L+1 of a per-lane array x.  Below the column
 // the bottom value is repeated (zero-gradient ghost); above it, either the top
@@ -680,8 +684,15 @@ __device__ __forceinline__ void flux_body(
     slow_rt<T, Lay, L, TR>(ln, rdx, rdy, rdz, vm, geo, U, V, Wz, th, RT);
 }
 
+// The flat float32 flux kernel with 4 levels per lane fits 4 waves per SIMD
+// without spilling (measured 0.977 ms against 1.027 ms at its natural 3);
+// the other variants keep the compiler's choice.
+template <typename T, int L, bool TR>
+constexpr int flux_waves() { return (sizeof(T) == 4 && L == 4 && !TR) ? 4 : 1; }
+
 template <typename T, class Lay, int L, bool TR>
-__global__ __launch_bounds__(BLOCK) void k_slow_flux(Group gr)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(flux_waves<T, L, TR>())))
+void k_slow_flux(Group gr)
 {
     const Where wh = locate(gr);
     if (!wh.active) return;
@@ -699,10 +710,30 @@ __global__ __launch_bounds__(BLOCK) void k_slow_flux(Group gr)
 // short step: horizontally explicit part, then the column solve
 // --------------------------------------------------------------------------
 
-// Solve the segment's tridiagonal system A x_{r-1} + B x_r + C x_{r+1} = D,
+// Reciprocal for the column solve: the hardware estimate refined by Newton
+// steps r <- r + r (1 - x r) (two in float64, one in float32), within an ulp
+// of 1/x for the normal, nonzero pivots a diagonally dominant system has; a
+// correctly rounded division costs about three times as many instructions.
+__device__ __forceinline__ double solve_rcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float solve_rcp(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    const float e = __builtin_fmaf(-x, r, 1.0f);
+    return __builtin_fmaf(r, e, r);
+}
+
+// Solve the segment's tridiagonal system A x_{r-1} + B x_r + C x_{r+1} = D
+// (SG lanes, L >= 2 rows each),
 // one row per level face, lane p holding rows p*L .. p*L+L-1.  A of the
 // first row and C of the last row of the column must be 0.
-template <typename S, int L>
+template <typename S, int L, int SG>
 __device__ __forceinline__ void segment_solve(int p, const S (&A)[L], const S (&B)[L],
                                               const S (&C)[L], const S (&D)[L], S (&x)[L])
 {
@@ -713,7 +744,7 @@ __device__ __forceinline__ void segment_solve(int p, const S (&A)[L], const S (&
 #pragma unroll
     for (int l = 0; l < n; ++l) {
         const S den = (l == 0) ? B[0] : B[l] - A[l] * gp[l - 1];
-        const S rden = S(1) / den;
+        const S rden = solve_rcp(den);
         gp[l] = (l < n - 1) ? C[l] * rden : S(0);
         const S rg = D[l], ra = (l == 0) ? -A[0] : S(0), rb = (l == n - 1) ? -C[l] : S(0);
         if (l == 0) {
@@ -733,24 +764,24 @@ __device__ __forceinline__ void segment_solve(int p, const S (&A)[L], const S (&
         yb[l] = yb[l] - gp[l] * yb[l + 1];
     }
     // reduced equation of the lane's last row, in X_{p-1}, X_p, X_{p+1}
-    const S ga = from_above(ya[0]), gb = from_above(yb[0]), gg = from_above(yg[0]);
+    const S ga = from_above<SG>(ya[0]), gb = from_above<SG>(yb[0]), gg = from_above<SG>(yg[0]);
     const S Ab = A[L - 1] * ya[n - 1];
     const S Bb = B[L - 1] + A[L - 1] * yb[n - 1] + C[L - 1] * ga;
     const S Cb = C[L - 1] * gb;
     const S Db = D[L - 1] - A[L - 1] * yg[n - 1] - C[L - 1] * gg;
-    const S rB = S(1) / Bb;
+    const S rB = solve_rcp(Bb);
     S a = Ab * rB, c = Cb * rB, d = Db * rB;
-    // parallel cyclic reduction over the 16 interface rows
+    // parallel cyclic reduction over the SG interface rows
 #pragma unroll
-    for (int s = 1; s < SEG; s <<= 1) {
-        const bool hasm = p >= s, hasp = p + s < SEG;
-        const S am = __shfl_up(a, (unsigned)s, SEG), cm = __shfl_up(c, (unsigned)s, SEG);
-        const S dm = __shfl_up(d, (unsigned)s, SEG);
-        const S ap = __shfl_down(a, (unsigned)s, SEG), cp = __shfl_down(c, (unsigned)s, SEG);
-        const S dp = __shfl_down(d, (unsigned)s, SEG);
+    for (int s = 1; s < SG; s <<= 1) {
+        const bool hasm = p >= s, hasp = p + s < SG;
+        const S am = __shfl_up(a, (unsigned)s, SG), cm = __shfl_up(c, (unsigned)s, SG);
+        const S dm = __shfl_up(d, (unsigned)s, SG);
+        const S ap = __shfl_down(a, (unsigned)s, SG), cp = __shfl_down(c, (unsigned)s, SG);
+        const S dp = __shfl_down(d, (unsigned)s, SG);
         const S amv = hasm ? am : S(0), cmv = hasm ? cm : S(0), dmv = hasm ? dm : S(0);
         const S apv = hasp ? ap : S(0), cpv = hasp ? cp : S(0), dpv = hasp ? dp : S(0);
-        const S rb2 = S(1) / (S(1) - a * cmv - c * apv);
+        const S rb2 = solve_rcp(S(1) - a * cmv - c * apv);
         const S dn = (d - a * dmv - c * dpv) * rb2;
         const S an = -a * amv * rb2;
         const S cn = -c * cpv * rb2;
@@ -759,7 +790,7 @@ __device__ __forceinline__ void segment_solve(int p, const S (&A)[L], const S (&
         d = dn;
     }
     const S X = d;
-    const S Xs = from_below(X);
+    const S Xs = from_below<SG>(X);
     const S Xb = (p == 0) ? S(0) : Xs;
 #pragma unroll
     for (int l = 0; l < n; ++l) x[l] = yg[l] + ya[l] * Xb + yb[l] * X;
@@ -767,13 +798,19 @@ __device__ __forceinline__ void segment_solve(int p, const S (&A)[L], const S (&
 }
 
 // Occupancy target of the short step (waves per SIMD), chosen so that the
-// register budget holds the lane's levels without spilling: 4 in float32
-// (3 with the terrain terms or a separate evaluation state), 2 with a
-// float64 solve (1 for float64 storage with the terrain terms), 1 for 8
-// levels per lane.
-template <typename T, typename S, int L, bool TR, bool EV>
+// register budget holds the lane's levels without spilling.  16-lane
+// segments: 4 in float32 (3 with the terrain terms or a separate evaluation
+// state), 2 with a float64 solve (1 for float64 storage with the terrain
+// terms), 1 for 8 levels per lane.  32-lane segments (float64 storage, half
+// the levels per lane): 4 with 2 levels per lane; with 4, 2 (1 with the
+// terrain terms).
+template <typename T, typename S, int L, bool TR, bool EV, int SG>
 constexpr int short_waves()
 {
+    if (SG == 32) {
+        if (L < 4) return 4;
+        return (sizeof(T) == 8 && TR) ? 1 : 2;
+    }
     if (L >= 8) return 1;
     if (sizeof(T) == 4 && sizeof(S) == 4) return (TR || EV) ? 3 : 4;
     if (sizeof(T) == 8 && TR && L >= 4) return 1;
@@ -783,15 +820,15 @@ constexpr int short_waves()
 // d p / d zeta at the lane's cell centres from a column's p: the mean of the
 // differences over the two level faces of the cell, the one inner face at the
 // lowest and highest cell.  rdzf[l] = 1/dzf of face k0+l.
-template <typename T, int L>
+template <int SG, typename T, int L>
 __device__ __forceinline__ void ddzeta(const T (&pp)[L], const T (&rdzf)[L], int p, int k0, int nz,
                                        T (&g)[L])
 {
     T dn[L];
-    const T pb = from_below(pp[L - 1]);
+    const T pb = from_below<SG>(pp[L - 1]);
 #pragma unroll
     for (int l = 0; l < L; ++l) dn[l] = (pp[l] - ((l == 0) ? pb : pp[l - 1])) * rdzf[l];
-    const T dna = from_above(dn[0]);
+    const T dna = from_above<SG>(dn[0]);
     (void)p;
 #pragma unroll
     for (int l = 0; l < L; ++l) {
@@ -806,9 +843,9 @@ __device__ __forceinline__ void ddzeta(const T (&pp)[L], const T (&rdzf)[L], int
 // (rpE, WE, tpE), while the increments are added to the first (rp, U, V, W,
 // tp): the second stage of the Runge-Kutta short step.  Without EV both are
 // the input state (forward-backward step).
-template <typename T, typename S, class Lay, int L, bool TR, bool EV>
+template <typename T, typename S, class Lay, int L, bool TR, bool EV, int SG>
 __device__ __forceinline__ void short_body(
-    const Lane<Lay, L> &ln, const double *__restrict__ vm, const double *__restrict__ geo,
+    const Lane<Lay, L, SG> &ln, const double *__restrict__ vm, const double *__restrict__ geo,
     double dtau_d, double beta_d, T rdx, T rdy,
     const T *__restrict__ rp, const T *__restrict__ U, const T *__restrict__ V,
     const T *__restrict__ W, const T *__restrict__ tp, const T *__restrict__ rpE,
@@ -869,17 +906,17 @@ __device__ __forceinline__ void short_body(
         ln.vmet(vm, VM_RDZF, rdzf_t);
         ln.vmet(vm, VM_DC, dc);
         T gc[L], g1[L], g2[L];
-        ddzeta(pc, rdzf_t, ln.p, ln.k0, ln.nz, gc);
-        ddzeta(pw, rdzf_t, ln.p, ln.k0, ln.nz, g1);
-        ddzeta(pe, rdzf_t, ln.p, ln.k0, ln.nz, g2);
+        ddzeta<SG>(pc, rdzf_t, ln.p, ln.k0, ln.nz, gc);
+        ddzeta<SG>(pw, rdzf_t, ln.p, ln.k0, ln.nz, g1);
+        ddzeta<SG>(pe, rdzf_t, ln.p, ln.k0, ln.nz, g2);
         const T fw = su0 / ju0, fe = su1 / ju1, fs = sv0 / jv0, fn = sv1 / jv1;
 #pragma unroll
         for (int l = 0; l < L; ++l) {
             cw[l] = (dc[l] * fw) * (T(0.5) * (g1[l] + gc[l]));
             ce[l] = (dc[l] * fe) * (T(0.5) * (gc[l] + g2[l]));
         }
-        ddzeta(ps, rdzf_t, ln.p, ln.k0, ln.nz, g1);
-        ddzeta(pn, rdzf_t, ln.p, ln.k0, ln.nz, g2);
+        ddzeta<SG>(ps, rdzf_t, ln.p, ln.k0, ln.nz, g1);
+        ddzeta<SG>(pn, rdzf_t, ln.p, ln.k0, ln.nz, g2);
 #pragma unroll
         for (int l = 0; l < L; ++l) {
             cs[l] = (dc[l] * fs) * (T(0.5) * (g1[l] + gc[l]));
@@ -956,7 +993,7 @@ __device__ __forceinline__ void short_body(
     const S mu = be * be * dts * dts;
     const S grav = (S)kGrav;
     const int p = ln.p;
-    const bool bot = (p == 0), top = (p == SEG - 1);
+    const bool bot = (p == 0), top = (p == SG - 1);
     S rdz[L], rdzf[L], av[L], bv[L];
     ln.vmet(vm, VM_RDZ, rdz);
     ln.vmet(vm, VM_RDZF, rdzf);
@@ -969,7 +1006,7 @@ __device__ __forceinline__ void short_body(
         const S rj = S(1) / (S)jcol;
         S df[L];
         ln.vmet(vm, VM_DF, df);
-        const S mxb = (S)from_below(mx[L - 1]), myb = (S)from_below(my[L - 1]);
+        const S mxb = (S)from_below<SG>(mx[L - 1]), myb = (S)from_below<SG>(my[L - 1]);
 #pragma unroll
         for (int l = 0; l < L; ++l) {
             const int k = ln.k0 + l;
@@ -980,15 +1017,15 @@ __device__ __forceinline__ void short_body(
             rdz[l] = rdz[l] * rj;
             rdzf[l] = rdzf[l] * rj;
         }
-        const S ea = from_above(Ef[0]);
+        const S ea = from_above<SG>(Ef[0]);
         Ef[L] = top ? S(0) : ea;
     } else {
         (void)mx; (void)my;
     }
-    const S rdz_b = from_below(rdz[L - 1]);   // 1/dz of the level below the lane
+    const S rdz_b = from_below<SG>(rdz[L - 1]);   // 1/dz of the level below the lane
 
     // theta_s on the lane's level faces k0..k0+L-1, and on face k0+L
-    const T th_b = from_below(thc[L - 1]);
+    const T th_b = from_below<SG>(thc[L - 1]);
     S thf[L + 1];
 #pragma unroll
     for (int l = 0; l < L; ++l) {
@@ -996,10 +1033,10 @@ __device__ __forceinline__ void short_body(
         thf[l] = (ln.k0 + l == 0) ? S(0) : av[l] * (S)thc[l] + bv[l] * tb;
     }
     {
-        const S t = from_above(thf[0]);
+        const S t = from_above<SG>(thf[0]);
         thf[L] = top ? S(0) : t;
     }
-    const T w_up = from_above(Wc[0]);
+    const T w_up = from_above<SG>(Wc[0]);
     S Wf[L + 1];
 #pragma unroll
     for (int l = 0; l < L; ++l) Wf[l] = (S)Wc[l];
@@ -1021,8 +1058,8 @@ __device__ __forceinline__ void short_body(
         pE[l] = be * ((S)P0c[l] + Cc[l] * thE[l]) + one_m_be * (S)pc[l];
         rEs[l] = be * rhE[l] + one_m_be * (S)rpold[l];
     }
-    const S C_b = from_below(Cc[L - 1]), thf_b = from_below(thf[L - 1]);
-    const S pE_b = from_below(pE[L - 1]), rEs_b = from_below(rEs[L - 1]);
+    const S C_b = from_below<SG>(Cc[L - 1]), thf_b = from_below<SG>(thf[L - 1]);
+    const S pE_b = from_below<SG>(pE[L - 1]), rEs_b = from_below<SG>(rEs[L - 1]);
 
     S A[L], B[L], C[L], D[L];
 #pragma unroll
@@ -1047,9 +1084,9 @@ __device__ __forceinline__ void short_body(
         D[l] = lid ? S(0) : fD;
     }
     S x[L];
-    segment_solve<S, L>(p, A, B, C, D, x);
+    segment_solve<S, L, SG>(p, A, B, C, D, x);
 
-    const S x_up = from_above(x[0]);
+    const S x_up = from_above<SG>(x[0]);
     const S xt = top ? S(0) : x_up;
     S rpn[L], tpn[L];
 #pragma unroll
@@ -1065,15 +1102,18 @@ __device__ __forceinline__ void short_body(
     ln.store(tpo, tpn);
 }
 
-template <typename T, typename S, class Lay, int L, bool TR, bool EV>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(short_waves<T, S, L, TR, EV>())))
+// SG lanes per column, kColsPerBlock columns per block of kColsPerBlock * SG
+// threads.
+template <typename T, typename S, class Lay, int L, bool TR, bool EV, int SG>
+__global__ __launch_bounds__(kColsPerBlock * SG)
+__attribute__((amdgpu_waves_per_eu(short_waves<T, S, L, TR, EV, SG>())))
 void k_short_step(Group gr, double frac)
 {
-    const Where wh = locate(gr);
+    const Where wh = locate<SG>(gr);
     if (!wh.active) return;
     const MemberDev *m = wh.m;
-    const Lane<Lay, L> ln(m->nx, m->ny, m->nz, wh.i, wh.j);
-    short_body<T, S, Lay, L, TR, EV>(
+    const Lane<Lay, L, SG> ln(m->nx, m->ny, m->nz, wh.i, wh.j);
+    short_body<T, S, Lay, L, TR, EV, SG>(
         ln, m->vm, m->geo, m->dt * frac, m->beta, (T)m->rdx, (T)m->rdy,
         (const T *)buf(m, gr.src, 0), (const T *)buf(m, gr.src, 1), (const T *)buf(m, gr.src, 2),
         (const T *)buf(m, gr.src, 3), (const T *)buf(m, gr.src, 4), (const T *)buf(m, gr.ev, 0),
@@ -1377,13 +1417,21 @@ struct RunFlux {
     }
 };
 
+// The float64 short step uses 32-lane segments (half the levels per lane,
+// so twice the waves per SIMD) when a column has at least 64 levels.  The
+// mixed form keeps 16 lanes: with 2 levels per lane the cyclic reduction's
+// float64 work per level doubles and outweighs the higher occupancy
+// (measured on 1024x1024x64: 1.035 ms with 16 lanes, 1.109 ms with 32).
 template <typename T, typename S, class Lay, int L>
 struct RunShort {
+    static constexpr bool kWide = sizeof(T) == 8 && L >= 4;
+    static constexpr int kSG = kWide ? 2 * SEG : SEG;
+    static constexpr int kL = kWide ? L / 2 : L;
     template <bool TR, bool EV>
     static void go(const Group &gr, double frac, hipStream_t s)
     {
-        hipLaunchKernelGGL((k_short_step<T, S, Lay, L, TR, EV>), dim3(gr.nblocks), dim3(BLOCK), 0, s,
-                           gr, frac);
+        hipLaunchKernelGGL((k_short_step<T, S, Lay, kL, TR, EV, kSG>), dim3(gr.nblocks),
+                           dim3(kColsPerBlock * kSG), 0, s, gr, frac);
     }
     static hipError_t run(const Group &gr, double frac, hipStream_t s)
     {

@@ -362,7 +362,9 @@ class Ensemble:
         return (m.value, e.value) if energy else m.value
 
     def tune(self):
-        out = (ctypes.c_int32 * 9)()
+        """Autotune per launch group; returns [prep, flux, short] tile x-extents
+        per group (at most 6 groups: flat and terrain, nz = 32, 64, 128)."""
+        out = (ctypes.c_int32 * (3 * 6))()
         ng = ctypes.c_int32()
         self._check(load().hv_ens_tune(self.handle, out, ctypes.byref(ng)))
         return [list(out[3 * g:3 * g + 3]) for g in range(ng.value)]

@@ -129,6 +129,9 @@ def test_ensemble_mixing_flat_and_terrain_members_is_bitwise(hv):
     print("case: ensemble flat + terrain", flush=True)
     for prec in ("fp64", "mixed"):
         e = hv.Ensemble(members, precision=prec)
+        if prec == "mixed":
+            # three launch groups: flat nz 32, terrain nz 32, terrain nz 64
+            assert len(e.tune()) == 3
         e.step(3, 4)
         for q, s in enumerate(members):
             d = hv.Domain(s, precision=prec)

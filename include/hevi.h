@@ -155,8 +155,7 @@ int hv_mass(hv_grid_t g, double *mass_out, double *energy_out);
  * per-kind totals and returns the total milliseconds and launch count of
  * one kind (a "launch" of HV_K_MASS is its two-kernel reduction).  Either
  * output pointer may be NULL. */
-enum { HV_K_SLOW_PREP = 0, HV_K_SLOW_FLUX = 1, HV_K_SHORT_STEP = 2, HV_K_MASS = 3, HV_K_DAMP = 4,
-       HV_K_COUNT = 5 };
+enum { HV_K_SLOW_PREP = 0, HV_K_SLOW_FLUX = 1, HV_K_SHORT_STEP = 2, HV_K_MASS = 3, HV_K_COUNT = 4 };
 int hv_trace(hv_grid_t g, int32_t on);
 int hv_trace_read(hv_grid_t g, int32_t kind, double *ms_total, int64_t *launches);
 
@@ -178,7 +177,10 @@ int hv_tune(hv_grid_t g, int32_t *tile_x_out);
  * momenta, t the model time at the end of the short step.  Each value then
  * relaxes implicitly, X <- (X + c X_target)/(1 + c), c = dtau (nu_lat of its
  * column + nu_top of its level; W's level face k uses level k); values with
- * rate 0 and W on the lids are left untouched.
+ * rate 0 and W on the lids are left untouched.  The relaxation runs inside
+ * the short-step kernel on the new values before they are stored (in the
+ * Runge-Kutta form after the second stage), so it reads only the two
+ * boundary states of the damped values.
  * Arguments: nu_lat nx*ny rates (1/s, >= 0, i fastest), nu_top nz rates;
  * bnd1[f], bnd2[f] boundary states in the layout of hv_state_init's fields
  * (W with zero lids); t1 < t2; time_now = model time of the current state

@@ -77,6 +77,7 @@ struct Group {
     int src, dst;           // state buffers read and written by this launch
     int ev;                 // short step: buffer of the explicit / old-time terms (src: forward-backward)
     int terrain;            // members of the group are terrain-following
+    int damp;               // short step: damp the new values (members with damping data)
 };
 
 // Blocks a member needs for a tile shape.
@@ -97,12 +98,10 @@ inline int partials_of(int nx, int ny)
 hipError_t launch_slow_prep(int prec, int layout, int L, const Group &gr, hipStream_t s);
 hipError_t launch_slow_flux(int prec, int layout, int L, const Group &gr, hipStream_t s);
 // Short step gr.src -> gr.dst of length (member dt) * frac, explicit and
-// old-time terms from gr.ev.
-hipError_t launch_short_step(int prec, int layout, int L, const Group &gr, double frac, hipStream_t s);
-// Lateral and upper damping of buffer gr.src in place, at model time
-// sums[2] + offset * dt, after a short step of length dt * frac.
-hipError_t launch_damp(int prec, int layout, int L, const Group &gr, double offset, double frac,
-                       hipStream_t s);
+// old-time terms from gr.ev; with gr.damp, damping at model time
+// sums[2] + offset * dt.
+hipError_t launch_short_step(int prec, int layout, int L, const Group &gr, double frac, double offset,
+                             hipStream_t s);
 // One thread per member of the group: model time += dt (end of a long step).
 hipError_t launch_clock(const Group &gr, hipStream_t s);
 // gr.blk maps blocks to (member, partial).  Sums the perturbation mass

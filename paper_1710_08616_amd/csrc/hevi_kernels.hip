@@ -799,20 +799,24 @@ __device__ __forceinline__ void segment_solve(int p, const S (&A)[L], const S (&
 
 // Occupancy target of the short step (waves per SIMD), chosen so that the
 // register budget holds the lane's levels without spilling.  16-lane
-// segments: 4 in float32 (3 with the terrain terms or a separate evaluation
-// state), 2 with a float64 solve (1 for float64 storage with the terrain
-// terms), 1 for 8 levels per lane.  32-lane segments (float64 storage, half
-// the levels per lane): 4 with 2 levels per lane; with 4, 2 (1 with the
-// terrain terms).
-template <typename T, typename S, int L, bool TR, bool EV, int SG>
+// segments: 4 in float32 (3 with the terrain terms, a separate evaluation
+// state or the damping; 2 with two of them), 2 with a float64 solve (1 for
+// float64 storage with the terrain terms), 1 for 8 levels per lane.  32-lane
+// segments (float64 storage, half the levels per lane): 4 with 2 levels per
+// lane (2 with the damping); with 4, 2 (1 with the terrain terms or the
+// damping).
+template <typename T, typename S, int L, bool TR, bool EV, int SG, bool DP>
 constexpr int short_waves()
 {
     if (SG == 32) {
-        if (L < 4) return 4;
-        return (sizeof(T) == 8 && TR) ? 1 : 2;
+        if (L < 4) return DP ? 2 : 4;
+        return (sizeof(T) == 8 && (TR || DP)) ? 1 : 2;
     }
     if (L >= 8) return 1;
-    if (sizeof(T) == 4 && sizeof(S) == 4) return (TR || EV) ? 3 : 4;
+    if (sizeof(T) == 4 && sizeof(S) == 4) {
+        const int extra = (TR ? 1 : 0) + (EV ? 1 : 0) + (DP ? 1 : 0);
+        return extra == 0 ? 4 : (extra == 1 ? 3 : 2);
+    }
     if (sizeof(T) == 8 && TR && L >= 4) return 1;
     return 2;
 }
@@ -838,14 +842,76 @@ __device__ __forceinline__ void ddzeta(const T (&pp)[L], const T (&rdzf)[L], int
     }
 }
 
+// Lateral and upper damping of one field's new values in registers (the
+// relaxation of the paper's Listing 1): the target is the boundary state
+// interpolated in time, mtratio (ref + bnd1) + tratio (ref + bnd2) - ref
+// (ref = 0 for the momenta), and each value with a nonzero rate relaxes
+// implicitly, v <- (v + c target) / (1 + c), c = dtau (nu_lat + nu_top).
+// W's lowest face (the lid) is left as it is.
+// (Set up twice per short step, for U and V and for the vertical fields, so
+// that nothing stays live across the column solve.)
+template <typename T, int L>
+struct DampLane {
+    bool any;
+    T cf[L], rc[L], mt, tr;   // cf = dtau nu (0: not damped), rc = 1/(1 + cf)
+};
+
+template <typename T, class Lay, int L, int SG>
+__device__ __forceinline__ DampLane<T, L> damp_setup(const Lane<Lay, L, SG> &ln, const MemberDev *m,
+                                                     double t, double dtau)
+{
+    DampLane<T, L> d;
+    const double nl = m->nu_lat[(size_t)ln.j * ln.nx + ln.i];
+    d.any = false;
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        const double nu = nl + m->nu_top[ln.k0 + l];
+        d.any = d.any || nu != 0.0;
+        d.cf[l] = nu != 0.0 ? (T)(dtau * nu) : T(0);
+        d.rc[l] = T(1) / (T(1) + d.cf[l]);
+    }
+    double r = (t - m->t1) / (m->t2 - m->t1);
+    r = r < 0.0 ? 0.0 : (r > 1.0 ? 1.0 : r);
+    d.tr = (T)r;
+    d.mt = (T)(1.0 - r);
+    return d;
+}
+
+template <typename T, class Lay, int L, int SG, bool TR, typename V>
+__device__ __forceinline__ void damp_field(const Lane<Lay, L, SG> &ln, const MemberDev *m,
+                                           const DampLane<T, L> &d, int f, V (&v)[L])
+{
+    if (!d.any) return;
+    T b1[L], b2[L], ref[L];
+    ln.template load<true>((const T *)m->bnd[0][f], 0, 0, b1);
+    ln.template load<true>((const T *)m->bnd[1][f], 0, 0, b2);
+#pragma unroll
+    for (int l = 0; l < L; ++l) ref[l] = T(0);
+    if (f == 0 || f == 4) {
+        if constexpr (TR) ln.template load<true>((const T *)m->ref[f == 0 ? 0 : 1], 0, 0, ref);
+        else ln.vmet(m->vm, f == 0 ? VM_RHO : VM_RT, ref);
+    }
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        const T tgt = d.mt * (ref[l] + b1[l]) + d.tr * (ref[l] + b2[l]) - ref[l];
+        const T x = (T)v[l];
+        const T y = (x + d.cf[l] * tgt) * d.rc[l];
+        const bool keep = d.cf[l] == T(0) || (f == 3 && ln.k0 + l == 0);
+        v[l] = keep ? v[l] : (V)y;
+    }
+}
+
 // EV: the explicit terms (p' of the horizontal pressure gradient) and the
 // old-time (1 - beta) parts of the vertical coupling come from a second state
 // (rpE, WE, tpE), while the increments are added to the first (rp, U, V, W,
 // tp): the second stage of the Runge-Kutta short step.  Without EV both are
 // the input state (forward-backward step).
-template <typename T, typename S, class Lay, int L, bool TR, bool EV, int SG>
+// DP: damp the new values toward the member's boundary data at model time
+// t_damp before storing them.
+template <typename T, typename S, class Lay, int L, bool TR, bool EV, int SG, bool DP>
 __device__ __forceinline__ void short_body(
-    const Lane<Lay, L, SG> &ln, const double *__restrict__ vm, const double *__restrict__ geo,
+    const Lane<Lay, L, SG> &ln, const MemberDev *dm, double t_damp,
+    const double *__restrict__ vm, const double *__restrict__ geo,
     double dtau_d, double beta_d, T rdx, T rdy,
     const T *__restrict__ rp, const T *__restrict__ U, const T *__restrict__ V,
     const T *__restrict__ W, const T *__restrict__ tp, const T *__restrict__ rpE,
@@ -984,6 +1050,11 @@ __device__ __forceinline__ void short_body(
         rt[l] = rpc[l] - dt * div;
         tt[l] = tpc[l] + dt * (RTc[l] - tdiv);
     }
+    if constexpr (DP) {
+        const DampLane<T, L> dl = damp_setup<T>(ln, dm, t_damp, dtau_d);
+        damp_field<T, Lay, L, SG, TR>(ln, dm, dl, 1, Up);
+        damp_field<T, Lay, L, SG, TR>(ln, dm, dl, 2, Vp);
+    }
     ln.store(Uo, Up);
     ln.store(Vo, Vp);
 
@@ -1097,6 +1168,12 @@ __device__ __forceinline__ void short_body(
         tpn[l] = thE[l] - f * (thf[l + 1] * xu - thf[l] * x[l]);
     }
     (void)bot;
+    if constexpr (DP) {
+        const DampLane<T, L> dl = damp_setup<T>(ln, dm, t_damp, dtau_d);
+        damp_field<T, Lay, L, SG, TR>(ln, dm, dl, 3, x);
+        damp_field<T, Lay, L, SG, TR>(ln, dm, dl, 0, rpn);
+        damp_field<T, Lay, L, SG, TR>(ln, dm, dl, 4, tpn);
+    }
     ln.store(Wo, x);
     ln.store(rpo, rpn);
     ln.store(tpo, tpn);
@@ -1104,17 +1181,33 @@ __device__ __forceinline__ void short_body(
 
 // SG lanes per column, kColsPerBlock columns per block of kColsPerBlock * SG
 // threads.
-template <typename T, typename S, class Lay, int L, bool TR, bool EV, int SG>
+// DP variants damp (members without damping data skip it) at the model time
+// sums[2] + offset * dt, the end of this short step.
+template <typename T, typename S, class Lay, int L, bool TR, bool EV, int SG, bool DP>
 __global__ __launch_bounds__(kColsPerBlock * SG)
-__attribute__((amdgpu_waves_per_eu(short_waves<T, S, L, TR, EV, SG>())))
-void k_short_step(Group gr, double frac)
+__attribute__((amdgpu_waves_per_eu(short_waves<T, S, L, TR, EV, SG, DP>())))
+void k_short_step(Group gr, double frac, double offset)
 {
     const Where wh = locate<SG>(gr);
     if (!wh.active) return;
     const MemberDev *m = wh.m;
     const Lane<Lay, L, SG> ln(m->nx, m->ny, m->nz, wh.i, wh.j);
-    short_body<T, S, Lay, L, TR, EV, SG>(
-        ln, m->vm, m->geo, m->dt * frac, m->beta, (T)m->rdx, (T)m->rdy,
+    constexpr bool kDamp = DP;
+    if (kDamp && m->nu_lat == nullptr) {
+        short_body<T, S, Lay, L, TR, EV, SG, false>(
+            ln, m, 0.0, m->vm, m->geo, m->dt * frac, m->beta, (T)m->rdx, (T)m->rdy,
+            (const T *)buf(m, gr.src, 0), (const T *)buf(m, gr.src, 1), (const T *)buf(m, gr.src, 2),
+            (const T *)buf(m, gr.src, 3), (const T *)buf(m, gr.src, 4), (const T *)buf(m, gr.ev, 0),
+            (const T *)buf(m, gr.ev, 3), (const T *)buf(m, gr.ev, 4), (T *)buf(m, gr.dst, 0),
+            (T *)buf(m, gr.dst, 1), (T *)buf(m, gr.dst, 2), (T *)buf(m, gr.dst, 3),
+            (T *)buf(m, gr.dst, 4), (const T *)m->slow[0], (const T *)m->slow[1],
+            (const T *)m->slow[2], (const T *)m->slow[3], (const T *)m->slow[4],
+            (const T *)m->slow[5], (const T *)m->slow[6]);
+        return;
+    }
+    short_body<T, S, Lay, L, TR, EV, SG, DP>(
+        ln, m, DP ? m->sums[2] + offset * m->dt : 0.0, m->vm, m->geo, m->dt * frac, m->beta,
+        (T)m->rdx, (T)m->rdy,
         (const T *)buf(m, gr.src, 0), (const T *)buf(m, gr.src, 1), (const T *)buf(m, gr.src, 2),
         (const T *)buf(m, gr.src, 3), (const T *)buf(m, gr.src, 4), (const T *)buf(m, gr.ev, 0),
         (const T *)buf(m, gr.ev, 3), (const T *)buf(m, gr.ev, 4), (T *)buf(m, gr.dst, 0),
@@ -1125,68 +1218,9 @@ void k_short_step(Group gr, double frac)
 }
 
 // --------------------------------------------------------------------------
-// lateral and upper damping (the relaxation of the paper's Listing 1): the
-// target of each prognostic is the boundary state interpolated in time,
-// mtratio (ref + bnd1) + tratio (ref + bnd2) - ref, and each value with a
-// nonzero rate relaxes implicitly, X <- (X + c X_target) / (1 + c),
-// c = dtau (nu_lat + nu_top).  Lanes whose levels all have rate 0 do no
-// memory traffic beyond the rates.
+// model clock of the damping: one thread per member, time += dt at the end
+// of a long step
 // --------------------------------------------------------------------------
-template <typename T, class Lay, int L, bool TR>
-__device__ __forceinline__ void damp_body(const Lane<Lay, L> &ln, const MemberDev *m, int b,
-                                          double t, double dtau)
-{
-    const double nl = m->nu_lat[(size_t)ln.j * ln.nx + ln.i];
-    double nu[L];
-    bool any = false;
-#pragma unroll
-    for (int l = 0; l < L; ++l) {
-        nu[l] = nl + m->nu_top[ln.k0 + l];
-        any = any || nu[l] != 0.0;
-    }
-    if (!any) return;
-    double tr = (t - m->t1) / (m->t2 - m->t1);
-    tr = tr < 0.0 ? 0.0 : (tr > 1.0 ? 1.0 : tr);
-    const T trt = (T)tr, mtt = (T)(1.0 - tr);
-    T cf[L];
-#pragma unroll
-    for (int l = 0; l < L; ++l) cf[l] = (T)(dtau * nu[l]);
-#pragma unroll
-    for (int f = 0; f < 5; ++f) {
-        T x[L], b1[L], b2[L], ref[L];
-        T *xp = (T *)buf(m, b, f);
-        ln.load(xp, 0, 0, x);
-        ln.template load<true>((const T *)m->bnd[0][f], 0, 0, b1);
-        ln.template load<true>((const T *)m->bnd[1][f], 0, 0, b2);
-#pragma unroll
-        for (int l = 0; l < L; ++l) ref[l] = T(0);
-        if (f == 0 || f == 4) {
-            if constexpr (TR) ln.template load<true>((const T *)m->ref[f == 0 ? 0 : 1], 0, 0, ref);
-            else ln.vmet(m->vm, f == 0 ? VM_RHO : VM_RT, ref);
-        }
-        T out[L];
-#pragma unroll
-        for (int l = 0; l < L; ++l) {
-            const T tgt = mtt * (ref[l] + b1[l]) + trt * (ref[l] + b2[l]) - ref[l];
-            const T y = (x[l] + cf[l] * tgt) / (T(1) + cf[l]);
-            const bool keep = nu[l] == 0.0 || (f == 3 && ln.k0 + l == 0);
-            out[l] = keep ? x[l] : y;
-        }
-        ln.store(xp, out);
-    }
-}
-
-template <typename T, class Lay, int L, bool TR>
-__global__ __launch_bounds__(BLOCK) void k_damp(Group gr, double offset, double frac)
-{
-    const Where wh = locate(gr);
-    if (!wh.active) return;
-    const MemberDev *m = wh.m;
-    if (!m->nu_lat) return;
-    const Lane<Lay, L> ln(m->nx, m->ny, m->nz, wh.i, wh.j);
-    damp_body<T, Lay, L, TR>(ln, m, gr.src, m->sums[2] + offset * m->dt, frac * m->dt);
-}
-
 __global__ void k_clock(Group gr)
 {
     const int q = (int)threadIdx.x;
@@ -1418,30 +1452,38 @@ struct RunFlux {
 };
 
 // The float64 short step uses 32-lane segments (half the levels per lane,
-// so twice the waves per SIMD) when a column has at least 64 levels.  The
+// so twice the waves per SIMD) for 64-level columns; with 128 levels a
+// 512-thread block cannot go below 2 waves per SIMD, whose 256 registers do
+// not hold 4 float64 levels per lane, so those keep 16 lanes.  The
 // mixed form keeps 16 lanes: with 2 levels per lane the cyclic reduction's
 // float64 work per level doubles and outweighs the higher occupancy
 // (measured on 1024x1024x64: 1.035 ms with 16 lanes, 1.109 ms with 32).
 template <typename T, typename S, class Lay, int L>
 struct RunShort {
-    static constexpr bool kWide = sizeof(T) == 8 && L >= 4;
+    static constexpr bool kWide = sizeof(T) == 8 && L == 4;
     static constexpr int kSG = kWide ? 2 * SEG : SEG;
     static constexpr int kL = kWide ? L / 2 : L;
-    template <bool TR, bool EV>
-    static void go(const Group &gr, double frac, hipStream_t s)
+    template <bool TR, bool EV, bool DP>
+    static void go(const Group &gr, double frac, double offset, hipStream_t s)
     {
-        hipLaunchKernelGGL((k_short_step<T, S, Lay, kL, TR, EV, kSG>), dim3(gr.nblocks),
-                           dim3(kColsPerBlock * kSG), 0, s, gr, frac);
+        hipLaunchKernelGGL((k_short_step<T, S, Lay, kL, TR, EV, kSG, DP>), dim3(gr.nblocks),
+                           dim3(kColsPerBlock * kSG), 0, s, gr, frac, offset);
     }
-    static hipError_t run(const Group &gr, double frac, hipStream_t s)
+    template <bool TR, bool EV>
+    static void go2(const Group &gr, double frac, double offset, hipStream_t s)
+    {
+        if (gr.damp) go<TR, EV, true>(gr, frac, offset, s);
+        else go<TR, EV, false>(gr, frac, offset, s);
+    }
+    static hipError_t run(const Group &gr, double frac, double offset, hipStream_t s)
     {
         const bool ev = gr.ev != gr.src;
         if (gr.terrain) {
-            if (ev) go<true, true>(gr, frac, s);
-            else go<true, false>(gr, frac, s);
+            if (ev) go2<true, true>(gr, frac, offset, s);
+            else go2<true, false>(gr, frac, offset, s);
         } else {
-            if (ev) go<false, true>(gr, frac, s);
-            else go<false, false>(gr, frac, s);
+            if (ev) go2<false, true>(gr, frac, offset, s);
+            else go2<false, false>(gr, frac, offset, s);
         }
         return hipGetLastError();
     }
@@ -1478,34 +1520,15 @@ hipError_t launch_slow_flux(int prec, int layout, int L, const Group &gr, hipStr
     return dispatch<RunFlux>(prec, layout, L, gr, s);
 }
 
-hipError_t launch_short_step(int prec, int layout, int L, const Group &gr, double frac, hipStream_t s)
+hipError_t launch_short_step(int prec, int layout, int L, const Group &gr, double frac, double offset,
+                             hipStream_t s)
 {
-    return dispatch<RunShort>(prec, layout, L, gr, frac, s);
+    return dispatch<RunShort>(prec, layout, L, gr, frac, offset, s);
 }
 
 hipError_t launch_sums(int prec, int layout, int L, const Group &gr, bool energy, hipStream_t s)
 {
     return dispatch<RunSums>(prec, layout, L, gr, energy, s);
-}
-
-template <typename T, typename S, class Lay, int L>
-struct RunDamp {
-    static hipError_t run(const Group &gr, double offset, double frac, hipStream_t s)
-    {
-        if (gr.terrain)
-            hipLaunchKernelGGL((k_damp<T, Lay, L, true>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr,
-                               offset, frac);
-        else
-            hipLaunchKernelGGL((k_damp<T, Lay, L, false>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr,
-                               offset, frac);
-        return hipGetLastError();
-    }
-};
-
-hipError_t launch_damp(int prec, int layout, int L, const Group &gr, double offset, double frac,
-                       hipStream_t s)
-{
-    return dispatch<RunDamp>(prec, layout, L, gr, offset, frac, s);
 }
 
 hipError_t launch_clock(const Group &gr, hipStream_t s)

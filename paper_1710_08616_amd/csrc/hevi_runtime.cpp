@@ -408,33 +408,30 @@ hipError_t enqueue_long_step(hv_ens *e, int n_short, const int r[3], hipStream_t
         for (int q = 0; q < n_short; ++q) {
             const int src = q == 0 ? P : R[(q - 1) & 1], dst = R[q & 1];
             const double f = frac[st] / n_short;
+            // damping (groups with damping data) at the end of this short
+            // step, model time t_n + (q + 1) dtau, inside the step's kernel
+            const double off = (q + 1) * f;
             for (auto &g : e->groups) {
-                const hv::Group gd = group_launch(e, g, KIND_SHORT, dst);
                 if (e->rk2) {
                     // X* = Phi(X, X, dtau/2) into buffer 3, then X+ = Phi(X, X*, dtau)
                     const hv::Group g1 = group_launch(e, g, KIND_SHORT, src, 3);
                     err = traced(e, s, HV_K_SHORT_STEP, [&] {
-                        return hv::launch_short_step(e->prec, e->layout, g.L, g1, 0.5 * f, s);
+                        return hv::launch_short_step(e->prec, e->layout, g.L, g1, 0.5 * f, 0.0, s);
                     });
                     if (err != hipSuccess) return err;
-                    const hv::Group g2 = group_launch(e, g, KIND_SHORT, src, dst, 3);
+                    hv::Group g2 = group_launch(e, g, KIND_SHORT, src, dst, 3);
+                    g2.damp = g.damping ? 1 : 0;
                     err = traced(e, s, HV_K_SHORT_STEP, [&] {
-                        return hv::launch_short_step(e->prec, e->layout, g.L, g2, f, s);
+                        return hv::launch_short_step(e->prec, e->layout, g.L, g2, f, off, s);
                     });
                 } else {
-                    const hv::Group gs = group_launch(e, g, KIND_SHORT, src, dst);
+                    hv::Group gs = group_launch(e, g, KIND_SHORT, src, dst);
+                    gs.damp = g.damping ? 1 : 0;
                     err = traced(e, s, HV_K_SHORT_STEP, [&] {
-                        return hv::launch_short_step(e->prec, e->layout, g.L, gs, f, s);
+                        return hv::launch_short_step(e->prec, e->layout, g.L, gs, f, off, s);
                     });
                 }
                 if (err != hipSuccess) return err;
-                if (g.damping) {
-                    // at the end of this short step: t_n + (q + 1) dtau
-                    err = traced(e, s, HV_K_DAMP, [&] {
-                        return hv::launch_damp(e->prec, e->layout, g.L, gd, (q + 1) * f, f, s);
-                    });
-                    if (err != hipSuccess) return err;
-                }
             }
         }
     }
@@ -927,7 +924,7 @@ int tune(hv_ens *e, int32_t *out, int32_t *ngroups)
         const hv::Group gr = group_launch(e, g, kind, e->roles[0], e->roles[1]);
         if (kind == KIND_PREP) return hv::launch_slow_prep(e->prec, e->layout, g.L, gr, s);
         if (kind == KIND_FLUX) return hv::launch_slow_flux(e->prec, e->layout, g.L, gr, s);
-        return hv::launch_short_step(e->prec, e->layout, g.L, gr, 1.0 / (3.0 * n_short), s);
+        return hv::launch_short_step(e->prec, e->layout, g.L, gr, 1.0 / (3.0 * n_short), 0.0, s);
     };
     int rc = HV_OK;
     for (auto &g : e->groups) {

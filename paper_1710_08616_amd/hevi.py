@@ -31,9 +31,9 @@ EXPORTS = ("hv_workspace_bytes", "hv_grid_create", "hv_state_init", "hv_step", "
            "hv_ens_workspace_bytes", "hv_ens_create", "hv_ens_state_init", "hv_ens_step",
            "hv_ens_state_read", "hv_ens_mass", "hv_ens_tune", "hv_ens_trace", "hv_ens_trace_read",
            "hv_ens_destroy", "hv_ens_last_error", "hv_diffuse", "hv_damping", "hv_ens_damping")
-K_SLOW_PREP, K_SLOW_FLUX, K_SHORT_STEP, K_MASS, K_DAMP = 0, 1, 2, 3, 4
+K_SLOW_PREP, K_SLOW_FLUX, K_SHORT_STEP, K_MASS = 0, 1, 2, 3
 KERNEL_KINDS = {"slow_prep": K_SLOW_PREP, "slow_flux": K_SLOW_FLUX, "short_step": K_SHORT_STEP,
-                "mass": K_MASS, "damp": K_DAMP}
+                "mass": K_MASS}
 
 _dp = ctypes.POINTER(ctypes.c_double)
 

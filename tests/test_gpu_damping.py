@@ -115,3 +115,32 @@ def test_damping_requires_reserved_workspace(hv):
         d.set_damping(bad)
     d.close()
     d2.close()
+
+
+def test_fp64_terrain_rk2_damping_together_match_oracle(hv, oracle):
+    """All optional terms at once: hills, the Runge-Kutta short step and the
+    damping, nz = 64 (the float64 32-lane short step)."""
+    s = _state(True, nz=64, seed=17)
+    print("case: damping + terrain + rk2 fp64 nz64", flush=True)
+    ref = oracle.step(s, n_long=2, short_rk2=True, time0=12.5)
+    got = _gpu(hv, s, "fp64", 2, "rk2", 12.5)
+    for name, a, b in zip(inputs.FIELD_NAMES, got, ref):
+        assert _rel(a, b) <= 1e-11, (name, _rel(a, b))
+
+
+def test_ensemble_with_damped_and_undamped_members(hv):
+    """Damping data are per member: a damped and an undamped member in one
+    launch group each match their own single-domain runs bitwise."""
+    a = _state(False, nz=32, seed=21)
+    b = _state(False, nz=32, seed=22)
+    b.damping = None
+    print("case: ensemble damping", flush=True)
+    e = hv.Ensemble([a, b], precision="mixed")
+    e.step(2, a.n_short)
+    for q, s in enumerate((a, b)):
+        d = hv.Domain(s, precision="mixed")
+        d.step(s.dt, 2, s.n_short)
+        for x, y in zip(e.read_all(q), d.read_all()):
+            assert np.array_equal(x, y)
+        d.close()
+    e.close()

@@ -160,12 +160,22 @@ int hv_trace(hv_grid_t g, int32_t on);
 int hv_trace_read(hv_grid_t g, int32_t kind, double *ms_total, int64_t *launches);
 
 /* Autotune: time each kernel kind (slow prep, slow flux, short step) of the
- * loaded state with every tile shape (16x1, 8x2, 4x4 columns of a 256-thread
- * block) and keep the fastest; results are bitwise independent of the shape.
- * The choice is appended to a plain-text cache ($HV_TUNE_CACHE, else
- * $HOME/.cache/hevi/tune.txt) that later grids of the same kind start from.
- * tile_x_out (may be NULL) receives the chosen x-extent of the three kinds.
- * Synchronises the stream; does not change the state. */
+ * loaded state with every launch configuration and keep the fastest; results
+ * are bitwise independent of the configuration.  A configuration is a tile
+ * shape (16x1, 8x2, 4x4 columns of a 256-thread block) and a block order:
+ * launch order, or XCD-banded (the first 8*P of the launch's blocks, P =
+ * blocks/8, are dealt so that each of the 8 XCDs runs a contiguous band of
+ * P tiles and shares its L2 between neighbours).  The choice is appended to
+ * a plain-text cache ($HV_TUNE_CACHE, else $HOME/.cache/hevi/tune.txt; one
+ * line "key c_prep c_flux c_short", c = shape index 0..2 for 16x1, 8x2, 4x4,
+ * plus 3 for the XCD-banded order; the last line of a key wins) that later
+ * grids of the same kind read at creation.  tile_x_out (may be NULL)
+ * receives the chosen x-extent of the three kinds, negated for the
+ * XCD-banded order.  Synchronises the stream; does not change the state.
+ * (Addressing: the slow-flux kernel reaches the arrays of a launch group by
+ * 32-bit byte offsets when every member's arrays are under 4 GiB, else by
+ * 64-bit addresses; HV_ADDR64=1 in the environment at creation forces the
+ * 64-bit form.  Both give bitwise-identical results.) */
 int hv_tune(hv_grid_t g, int32_t *tile_x_out);
 
 /* Lateral and upper damping, the relaxation kernel of the paper's Listing 1

@@ -36,6 +36,7 @@
 #include "hevi_kernels.h"
 
 #include <cstdint>
+#include <type_traits>
 
 namespace hv {
 namespace {
@@ -49,6 +50,16 @@ constexpr double kGrav = 9.80665;
 template <typename T, int L>
 using vec_t = T __attribute__((ext_vector_type(L)));
 
+// Pointer into device global memory.  Every array a kernel reaches through
+// a member table is global, but the compiler cannot see that through the
+// table and emits flat memory instructions; with the address space explicit
+// it emits global ones, which take a scalar base and a 32-bit per-lane
+// offset.  Which of the two schedules better differs per kernel (measured:
+// the float64 slow flux gains 16% with global instructions, the float32 one
+// loses 13%), so it is a property of the addressing below.
+template <typename T>
+using gptr = T __attribute__((address_space(1))) *;
+
 __device__ __forceinline__ int wrapc(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
 // Block -> (member, tile) -> this segment's column.  A tile is (1 << ti_log2)
@@ -58,13 +69,29 @@ struct Where {
     int i, j;
     bool active;
 };
+// Launch order of the blocks.  Workgroups go to the 8 XCDs (each with its own
+// L2) in turn, so in launch order neighbouring tiles land on different L2s.
+// The XCD-banded order hands XCD x the contiguous run x*P .. x*P + P-1 of the
+// first 8P blocks (P = nblocks / 8), so that most neighbour columns a tile
+// reads sit in the same L2; the autotuner decides whether it pays.
+__device__ __forceinline__ int block_order(const Group &gr)
+{
+    int b = (int)blockIdx.x;
+    if (gr.xcd) {
+        const int per = gr.nblocks >> 3;
+        if (b < (per << 3)) b = (b & 7) * per + (b >> 3);
+    }
+    return b;
+}
+
 template <int SG = SEG>
 __device__ __forceinline__ Where locate(const Group &gr)
 {
     Where w;
-    int t = (int)blockIdx.x, id = gr.first;
+    const int b = block_order(gr);
+    int t = b, id = gr.first;
     if (gr.nm > 1) {
-        const unsigned v = gr.blk[blockIdx.x];
+        const unsigned v = gr.blk[b];
         t = (int)(v & 0xFFFFFFu);
         id = (int)(v >> 24);
     }
@@ -81,17 +108,38 @@ __device__ __forceinline__ Where locate(const Group &gr)
 // Storage orders of a 3D field with nz levels per column.
 struct KIJ {
     static constexpr bool kContig = true;
+    static constexpr bool kOff32 = false;
+    static constexpr bool kGlobal = false;
     __device__ static size_t at(int i, int j, int k, int nx, int ny, int nz)
     {
         return ((size_t)j * nx + i) * nz + k;
     }
+    __device__ static unsigned at32(int i, int j, int k, int nx, int ny, int nz)
+    {
+        return ((unsigned)j * nx + i) * nz + k;
+    }
 };
 struct IJK {
     static constexpr bool kContig = false;
+    static constexpr bool kOff32 = false;
+    static constexpr bool kGlobal = false;
     __device__ static size_t at(int i, int j, int k, int nx, int ny, int nz)
     {
         return ((size_t)k * ny + j) * nx + i;
     }
+    __device__ static unsigned at32(int i, int j, int k, int nx, int ny, int nz)
+    {
+        return ((unsigned)k * ny + j) * nx + i;
+    }
+};
+// The same order addressed by 32-bit byte offsets from the array's base (one
+// scalar base register per array, no per-lane 64-bit address arithmetic),
+// with flat or (G) global memory instructions; valid while every array of
+// the member is under 4 GiB, which the host checks before it picks these.
+template <class Base, bool G>
+struct Off32 : Base {
+    static constexpr bool kOff32 = true;
+    static constexpr bool kGlobal = G;
 };
 
 // Field f of state buffer b.
@@ -117,14 +165,28 @@ struct Lane {
     {
         return Lay::at(wrapc(i + di, nx), wrapc(j + dj, ny), k0, nx, ny, nz);
     }
+    template <typename U>
+    using ptr_t = std::conditional_t<Lay::kGlobal, gptr<U>, U *>;
+    // element of the lane's column (i+di, j+dj) at level k0 + l
+    template <typename T>
+    __device__ ptr_t<T> elem(T *a, int di, int dj, int l = 0) const
+    {
+        if constexpr (Lay::kOff32) {
+            const unsigned e = Lay::at32(wrapc(i + di, nx), wrapc(j + dj, ny), k0, nx, ny, nz) +
+                               (unsigned)l * (unsigned)kstride;
+            using B = std::conditional_t<std::is_const_v<T>, const char, char>;
+            return (ptr_t<T>)((ptr_t<B>)a + (size_t)(e * (unsigned)sizeof(T)));
+        } else {
+            return (ptr_t<T>)a + off(di, dj) + (size_t)l * kstride;
+        }
+    }
     // Load the lane's L levels of column (i+di, j+dj).  NT = non-temporal:
     // for data no other column reads in this kernel.
     template <bool NT = false, typename T>
     __device__ void load(const T *__restrict__ a, int di, int dj, T (&x)[L]) const
     {
-        const T *q = a + off(di, dj);
         if constexpr (Lay::kContig) {
-            const vec_t<T, L> *vq = reinterpret_cast<const vec_t<T, L> *>(q);
+            const auto vq = (ptr_t<const vec_t<T, L>>)elem(a, di, dj);
             vec_t<T, L> t;
             if constexpr (NT) t = __builtin_nontemporal_load(vq);
             else t = *vq;
@@ -133,8 +195,9 @@ struct Lane {
         } else {
 #pragma unroll
             for (int l = 0; l < L; ++l) {
-                if constexpr (NT) x[l] = __builtin_nontemporal_load(q + (size_t)l * kstride);
-                else x[l] = q[(size_t)l * kstride];
+                const ptr_t<const T> q = elem(a, di, dj, l);
+                if constexpr (NT) x[l] = __builtin_nontemporal_load(q);
+                else x[l] = *q;
             }
         }
     }
@@ -143,15 +206,14 @@ struct Lane {
     template <typename T, typename S>
     __device__ void store(T *__restrict__ a, const S (&x)[L]) const
     {
-        T *q = a + off(0, 0);
         if constexpr (Lay::kContig) {
             vec_t<T, L> t;
 #pragma unroll
             for (int l = 0; l < L; ++l) t[l] = (T)x[l];
-            __builtin_nontemporal_store(t, reinterpret_cast<vec_t<T, L> *>(q));
+            __builtin_nontemporal_store(t, (ptr_t<vec_t<T, L>>)elem(a, 0, 0));
         } else {
 #pragma unroll
-            for (int l = 0; l < L; ++l) __builtin_nontemporal_store((T)x[l], q + (size_t)l * kstride);
+            for (int l = 0; l < L; ++l) __builtin_nontemporal_store((T)x[l], elem(a, 0, 0, l));
         }
     }
     // per-column geometry value f of column (i+di, j+dj)
@@ -403,19 +465,17 @@ __device__ __forceinline__ void slow_su(const Lane<Lay, L> &ln, T rdx, T rdy, co
     T ue[L + 4];
     extend2(ux[2], ue, ln.p, false);
     const bool top = (ln.p == SEG - 1);
-    const T Wm_a = from_above(Wm[0]), W0_a = from_above(W0[0]);
-    const T Wm_up = top ? T(0) : Wm_a;
-    const T W0_up = top ? T(0) : W0_a;
+    // fluxes through the lane's level faces k0 .. k0+L-1; face k0+L is the
+    // first face of the lane above (the rigid lid for the top lane)
     T fz[L + 1];
 #pragma unroll
-    for (int l = 0; l <= L; ++l) {
-        const int kf = ln.k0 + l;
-        const T wa = (l < L) ? Wm[l] : Wm_up;
-        const T wb = (l < L) ? W0[l] : W0_up;
-        const T m = T(0.5) * (wa + wb);
+    for (int l = 0; l < L; ++l) {
+        const T m = T(0.5) * (Wm[l] + W0[l]);
         const T q = kface(ue[l], ue[l + 1], ue[l + 2], ue[l + 3], m);
-        fz[l] = (kf == 0 || kf == ln.nz) ? T(0) : m * q;
+        fz[l] = (ln.k0 + l == 0) ? T(0) : m * q;
     }
+    const T fz_a = from_above(fz[0]);
+    fz[L] = top ? T(0) : fz_a;
     T out[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) {
@@ -478,19 +538,17 @@ __device__ __forceinline__ void slow_sv(const Lane<Lay, L> &ln, T rdx, T rdy, co
     T ve[L + 4];
     extend2(vy[2], ve, ln.p, false);
     const bool top = (ln.p == SEG - 1);
-    const T Wm_a = from_above(Wm[0]), W0_a = from_above(W0[0]);
-    const T Wm_up = top ? T(0) : Wm_a;
-    const T W0_up = top ? T(0) : W0_a;
+    // fluxes through the lane's level faces k0 .. k0+L-1; face k0+L is the
+    // first face of the lane above (the rigid lid for the top lane)
     T fz[L + 1];
 #pragma unroll
-    for (int l = 0; l <= L; ++l) {
-        const int kf = ln.k0 + l;
-        const T wa = (l < L) ? Wm[l] : Wm_up;
-        const T wb = (l < L) ? W0[l] : W0_up;
-        const T m = T(0.5) * (wa + wb);
+    for (int l = 0; l < L; ++l) {
+        const T m = T(0.5) * (Wm[l] + W0[l]);
         const T q = kface(ve[l], ve[l + 1], ve[l + 2], ve[l + 3], m);
-        fz[l] = (kf == 0 || kf == ln.nz) ? T(0) : m * q;
+        fz[l] = (ln.k0 + l == 0) ? T(0) : m * q;
     }
+    const T fz_a = from_above(fz[0]);
+    fz[L] = top ? T(0) : fz_a;
     T out[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) {
@@ -553,13 +611,16 @@ __device__ __forceinline__ void slow_sw(const Lane<Lay, L> &ln, T rdx, T rdy,
         jv1 = (T)ln.geo(geo, GEO_JV, 0, 1);
         jc = (T)ln.geo(geo, GEO_J, 0, 0);
     }
-    // vertical fluxes at the cell centres cc = k0-1 .. k0+L-1
+    // vertical fluxes at the cell centres cc = k0-1 .. k0+L-1; the first is
+    // the last of the lane below (unused on the bottom lane, whose first
+    // level face is the lower lid)
     T fz[L + 1];
 #pragma unroll
-    for (int l = 0; l <= L; ++l) {
+    for (int l = 1; l <= L; ++l) {
         const T m = T(0.5) * (We[l + 1] + We[l + 2]);
         fz[l] = m * kface(we[l], we[l + 1], we[l + 2], we[l + 3], m);
     }
+    fz[0] = from_below(fz[L]);
     T out[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) {
@@ -624,25 +685,24 @@ __device__ __forceinline__ void slow_rt(const Lane<Lay, L> &ln, T rdx, T rdy, co
     T te[L + 4];
     extend2(tx[2], te, ln.p, false);
     const bool top = (ln.p == SEG - 1);
-    const T W_a = from_above(W0[0]);
-    const T W_up = top ? T(0) : W_a;
-    T a[L + 1], b[L + 1];
+    T a[L], b[L];
 #pragma unroll
-    for (int l = 0; l <= L; ++l) {
-        int k = ln.k0 + l;
-        k = k >= ln.nz ? ln.nz - 1 : k;
-        a[l] = (T)vm[(size_t)VM_A * ln.nz + k];
-        b[l] = (T)vm[(size_t)VM_B * ln.nz + k];
+    for (int l = 0; l < L; ++l) {
+        a[l] = (T)vm[(size_t)VM_A * ln.nz + ln.k0 + l];
+        b[l] = (T)vm[(size_t)VM_B * ln.nz + ln.k0 + l];
     }
+    // fluxes through the lane's level faces k0 .. k0+L-1; face k0+L is the
+    // first face of the lane above (the rigid lid for the top lane)
     T gz[L + 1];
 #pragma unroll
-    for (int l = 0; l <= L; ++l) {
-        const int kf = ln.k0 + l;
-        const T m = (l < L) ? W0[l] : W_up;
+    for (int l = 0; l < L; ++l) {
+        const T m = W0[l];
         const T tl = kface(te[l], te[l + 1], te[l + 2], te[l + 3], m);
         const T tcen = a[l] * te[l + 2] + b[l] * te[l + 1];
-        gz[l] = (kf == 0 || kf == ln.nz) ? T(0) : m * (tl - tcen);
+        gz[l] = (ln.k0 + l == 0) ? T(0) : m * (tl - tcen);
     }
+    const T gz_a = from_above(gz[0]);
+    gz[L] = top ? T(0) : gz_a;
     T out[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) {
@@ -1441,12 +1501,21 @@ struct RunPrep {
 
 template <typename T, typename S, class Lay, int L>
 struct RunFlux {
-    static hipError_t run(const Group &gr, hipStream_t s)
+    template <class A>
+    static void go(const Group &gr, hipStream_t s)
     {
         if (gr.terrain)
-            hipLaunchKernelGGL((k_slow_flux<T, Lay, L, true>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr);
+            hipLaunchKernelGGL((k_slow_flux<T, A, L, true>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr);
         else
-            hipLaunchKernelGGL((k_slow_flux<T, Lay, L, false>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr);
+            hipLaunchKernelGGL((k_slow_flux<T, A, L, false>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr);
+    }
+    // The slow flux is instruction-heavy enough that 32-bit array offsets pay
+    // (float32: 0.973 -> 0.895 ms, float64: 2.50 -> 2.09 ms on 1024x1024x64);
+    // the host selects them when every array fits in 4 GiB.
+    static hipError_t run(const Group &gr, hipStream_t s)
+    {
+        if (gr.off32) go<Off32<Lay, sizeof(T) == 8>>(gr, s);
+        else go<Lay>(gr, s);
         return hipGetLastError();
     }
 };

@@ -37,8 +37,11 @@ thread_local std::string g_global_error = "no error";
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-// tile shapes the autotuner tries: log2 of the columns along x (16x1, 8x2, 4x4)
+// tile shapes the autotuner tries: log2 of the columns along x (16x1, 8x2, 4x4);
+// a launch configuration is a shape and a block order (launch order or
+// XCD-banded): index c = shape + 3 * banded, c in 0..5
 constexpr int kShapes[3] = {4, 3, 2};
+constexpr int kConfigs = 6;
 enum { KIND_PREP = 0, KIND_FLUX = 1, KIND_SHORT = 2, NKIND = 3 };
 
 struct MemberHost {
@@ -58,13 +61,14 @@ struct GroupHost {
     int L = 0;
     bool terrain = false;
     bool damping = false;      // some member has damping data
+    bool off32 = false;        // every member's arrays fit 32-bit byte offsets
     std::vector<int> ids;
     int *d_ids = nullptr;
     unsigned *d_blk[3] = {};   // per tile shape: block -> slot << 24 | tile (nm > 1)
     unsigned *d_pblk = nullptr;  // block -> slot << 24 | partial (nm > 1)
     int nblocks[3] = {};
     int npblocks = 0;
-    int shape[NKIND] = {0, 0, 0};  // index into kShapes per kernel kind
+    int shape[NKIND] = {0, 0, 0};  // launch configuration per kernel kind (0..kConfigs-1)
 };
 
 struct GraphEntry {
@@ -333,15 +337,17 @@ hv::Group group_launch(const hv_ens *e, const GroupHost &g, int kind, int src, i
     gr.dst = dst;
     gr.ev = ev < 0 ? src : ev;
     gr.terrain = g.terrain ? 1 : 0;
+    gr.off32 = g.off32 ? 1 : 0;
     if (kind < 0) {
         gr.blk = g.d_pblk;
         gr.nblocks = g.npblocks;
         gr.ti_log2 = 4;
     } else {
-        const int sh = g.shape[kind];
+        const int sh = g.shape[kind] % 3;
         gr.blk = g.d_blk[sh];
         gr.nblocks = g.nblocks[sh];
         gr.ti_log2 = kShapes[sh];
+        gr.xcd = g.shape[kind] / 3;
     }
     gr.first = g.ids[0];
     return gr;
@@ -461,7 +467,8 @@ void drop_graphs(hv_ens *e)
     e->graphs.clear();
 }
 
-// ---- autotuner cache: one line per key, "key ti_prep ti_flux ti_short" ----
+// ---- autotuner cache: one line per key, "key c_prep c_flux c_short" with
+// the launch configuration index of each kind ----
 std::string cache_path()
 {
     if (const char *p = std::getenv("HV_TUNE_CACHE")) return p;
@@ -491,7 +498,7 @@ bool cache_lookup(const std::string &key, int shape[NKIND])
     int a, b, c;
     bool found = false;
     while (f >> k >> a >> b >> c)
-        if (k == key && a >= 0 && a < 3 && b >= 0 && b < 3 && c >= 0 && c < 3) {
+        if (k == key && a >= 0 && a < kConfigs && b >= 0 && b < kConfigs && c >= 0 && c < kConfigs) {
             shape[0] = a; shape[1] = b; shape[2] = c;
             found = true;
         }
@@ -597,6 +604,11 @@ int ens_create(hv_ens *e, int n, const hv_grid_desc *descs, void *ws, size_t byt
         g.ids = gm[gi];
         g.L = descs[g.ids[0]].nz / hv::kSeg;
         g.terrain = descs[g.ids[0]].terrain != nullptr;
+        // HV_ADDR64=1 keeps 64-bit addressing everywhere (same results)
+        const char *a64 = std::getenv("HV_ADDR64");
+        g.off32 = !(a64 && a64[0] == '1');
+        for (int q : g.ids)
+            if ((size_t)descs[q].nx * descs[q].ny * descs[q].nz * e->esize > 0xFFFFFFFFull) g.off32 = false;
         const int nm = (int)g.ids.size();
         if (n > 255) return fail(nullptr, HV_ERR_ARG, "at most 255 members");
         int *dst = (int *)(base + p.group_off[gi]);
@@ -931,7 +943,7 @@ int tune(hv_ens *e, int32_t *out, int32_t *ngroups)
         for (int kind = 0; kind < NKIND && rc == HV_OK; ++kind) {
             float best = 1e30f;
             int best_s = g.shape[kind];
-            for (int s = 0; s < 3 && rc == HV_OK; ++s) {
+            for (int s = 0; s < kConfigs && rc == HV_OK; ++s) {
                 g.shape[kind] = s;
                 // the slow arrays the flux and short step read must hold this stage's values
                 if ((r = launch(g, KIND_PREP, e->stream)) != hipSuccess ||
@@ -960,7 +972,10 @@ int tune(hv_ens *e, int32_t *out, int32_t *ngroups)
     if (ngroups) *ngroups = (int32_t)e->groups.size();
     if (out)
         for (size_t gi = 0; gi < e->groups.size(); ++gi)
-            for (int k = 0; k < NKIND; ++k) out[gi * NKIND + k] = 1 << kShapes[e->groups[gi].shape[k]];
+            for (int k = 0; k < NKIND; ++k) {
+                const int c = e->groups[gi].shape[k];
+                out[gi * NKIND + k] = (c / 3 ? -1 : 1) * (1 << kShapes[c % 3]);
+            }
     return HV_OK;
 }
 

@@ -64,6 +64,9 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
                            "(or python -m paper_1710_08616_amd.build_lib)")
+    # torch first: its HIP runtime (same soname) is then the one the library
+    # binds to, so workspace, streams and kernels share one runtime
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     L.hv_workspace_bytes.restype = ctypes.c_size_t
     L.hv_workspace_bytes.argtypes = [ctypes.POINTER(GridDesc)]
@@ -247,8 +250,9 @@ class Domain:
         return (m.value, e.value) if energy else m.value
 
     def tune(self):
-        """Autotune the tile shapes; returns the chosen x-extent per kernel kind
-        (slow prep, slow flux, short step)."""
+        """Autotune the launch configurations; returns the chosen tile x-extent
+        per kernel kind (slow prep, slow flux, short step), negative where the
+        XCD-banded block order won."""
         out = (ctypes.c_int32 * 3)()
         self._check(load().hv_tune(self.handle, out))
         return list(out)

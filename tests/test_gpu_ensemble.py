@@ -76,13 +76,64 @@ def test_tuned_tile_shapes_give_identical_results(hv, tmp_path, monkeypatch):
     e0.close()
     e1 = hv.Ensemble(ms, precision="fp32")
     shapes = e1.tune()
-    assert len(shapes) == 2 and all(x in (16, 8, 4) for g in shapes for x in g)
+    assert len(shapes) == 2 and all(abs(x) in (16, 8, 4) for g in shapes for x in g)
     e1.step(2, 4)
     for q in range(len(ms)):
         for a, b in zip(e1.read_all(q), ref[q]):
             assert np.array_equal(a, b)
     e1.close()
     assert (tmp_path / "tune.txt").exists()
+
+
+def test_every_launch_configuration_is_bitwise(hv, tmp_path, monkeypatch):
+    """Each of the six launch configurations (three tile shapes, launch order
+    or XCD-banded order), forced through the tune cache read at creation,
+    gives the untuned result bitwise.  90 16x1 tiles: the banded order deals
+    88 of them and leaves a tail of 2; two members make it the grouped form."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("HV_TUNE_CACHE", str(cache))
+    ms = [inputs.make_state(40, 30, 32, seed=31, dt=8.0, n_short=3, noise=0.4, u_bg=6.0),
+          inputs.make_state(21, 19, 32, seed=32, dt=7.0, n_short=3, noise=0.4, u_bg=-4.0)]
+    print("case: forced launch configurations", flush=True)
+    for group in ([ms[0]], ms):
+        base = hv.Ensemble(group, precision="mixed")
+        base.step(2, 3)
+        ref = [base.read_all(q) for q in range(len(group))]
+        base.tune()
+        base.close()
+        key = cache.read_text().split()[-4]
+        for c in range(6):
+            with open(cache, "a") as f:
+                f.write(f"{key} {c} {(c + 2) % 6} {(c + 4) % 6}\n")
+            e = hv.Ensemble(group, precision="mixed")
+            e.step(2, 3)
+            for q in range(len(group)):
+                for name, a, b in zip(inputs.FIELD_NAMES, e.read_all(q), ref[q]):
+                    assert np.array_equal(a, b), (len(group), c, q, name)
+            e.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_32_and_64_bit_addressing_are_bitwise(hv, monkeypatch, prec):
+    """The slow flux addresses arrays under 4 GiB with 32-bit offsets;
+    HV_ADDR64=1 (read at creation) keeps 64-bit addressing.  Flat and
+    terrain members, both layouts: the results must not differ by a bit."""
+    dx = 2000.0
+    h = inputs.orography(24, 20, dx, dx, 41, hmax=1200.0, hills=2, smin=3 * dx, smax=6 * dx)
+    ms = [inputs.make_state(24, 20, 32, seed=41, terrain=h, u_bg=5.0, noise=0.4, n_short=3),
+          inputs.make_state(19, 23, 64, seed=42, u_bg=-6.0, noise=0.4, n_short=3)]
+    print(f"case: 32- vs 64-bit addressing {prec}", flush=True)
+    for layout in ("kij", "ijk"):
+        res = []
+        for flag in ("0", "1"):
+            monkeypatch.setenv("HV_ADDR64", flag)
+            e = hv.Ensemble(ms, precision=prec, layout=layout)
+            e.step(2, 3)
+            res.append([e.read_all(q) for q in range(len(ms))])
+            e.close()
+        for q in range(len(ms)):
+            for name, a, b in zip(inputs.FIELD_NAMES, res[0][q], res[1][q]):
+                assert np.array_equal(a, b), (layout, q, name)
 
 
 def test_graph_replay_equals_direct_launches(hv):

@@ -744,14 +744,15 @@ __device__ __forceinline__ void flux_body(
     slow_rt<T, Lay, L, TR>(ln, rdx, rdy, rdz, vm, geo, U, V, Wz, th, RT);
 }
 
-// The flat float32 flux kernel with 4 levels per lane fits 4 waves per SIMD
-// without spilling (measured 0.977 ms against 1.027 ms at its natural 3);
+// The flat float32 flux kernel with 4 contiguous levels per lane fits 4 waves
+// per SIMD without spilling (measured 0.977 ms against 1.027 ms at its natural
+// 3; the i-fastest form would spill there);
 // the other variants keep the compiler's choice.
-template <typename T, int L, bool TR>
-constexpr int flux_waves() { return (sizeof(T) == 4 && L == 4 && !TR) ? 4 : 1; }
+template <typename T, class Lay, int L, bool TR>
+constexpr int flux_waves() { return (sizeof(T) == 4 && L == 4 && !TR && Lay::kContig) ? 4 : 1; }
 
 template <typename T, class Lay, int L, bool TR>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(flux_waves<T, L, TR>())))
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(flux_waves<T, Lay, L, TR>())))
 void k_slow_flux(Group gr)
 {
     const Where wh = locate(gr);

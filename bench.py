@@ -56,8 +56,15 @@ def short_step_bytes(b: int, cells: int) -> int:
 
 
 def kernel_digest() -> str:
+    """Digest of the kernel source with comments and blank lines removed, so
+    that a comment edit does not invalidate the recorded counters."""
     src = os.path.join(ROOT, "paper_1710_08616_amd", "csrc", "hevi_kernels.hip")
-    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    code = []
+    for line in open(src, encoding="utf-8"):
+        line = line.split("//", 1)[0].rstrip()
+        if line:
+            code.append(line)
+    return hashlib.sha256("\n".join(code).encode()).hexdigest()[:16]
 
 
 def read_traffic(prec: str):
@@ -83,7 +90,7 @@ def time_precision(hevi, s, prec, steps, warmup, layout="kij", keep=False, short
     d = hevi.Domain(s, precision=prec, layout=layout, short=short)
     tiles = None
     if tune:
-        # the autotuner times each tile shape per kernel kind on this state
+        # the autotuner times each launch configuration per kernel kind on this state
         # (results are bitwise independent of the shape; the state is left
         # unchanged)
         tiles = d.tune()
@@ -166,7 +173,7 @@ def accuracy_vs_oracle(hevi, sub, precs):
 
 
 def time_ensemble(hevi, members, prec, steps, warmup, layout="kij", tune=True):
-    """The batched ensemble: autotune tile shapes, warm up, then time `steps`
+    """The batched ensemble: autotune launch configurations, warm up, then time `steps`
     long steps of all members (each with its own dt) with per-kernel events."""
     import torch
     n_short = members[0].n_short

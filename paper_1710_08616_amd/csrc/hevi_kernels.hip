@@ -6,8 +6,9 @@
 // contiguous, so each per-lane access is one vector load and a wavefront
 // touches 4 columns of contiguous memory.  Vertical neighbours live in the
 // adjacent lane of the same segment (segment shuffles); horizontal neighbours
-// are other columns and come through L1/L2.  A block of 256 threads covers 16
-// consecutive columns.
+// are other columns and come through L1/L2.  A block of 256 threads covers a
+// tile of 16 columns (16x1, 8x2 or 4x4, in launch or XCD-banded order, as the
+// autotuner chose; the results do not depend on it).
 //
 // The per-column tridiagonal system of the vertically implicit part is solved
 // without leaving the segment: every lane eliminates its interior rows in

@@ -23,6 +23,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <filesystem>
 #include <fstream>
 #include <new>
 #include <sstream>
@@ -509,12 +510,9 @@ void cache_store(const std::string &key, const int shape[NKIND])
 {
     const std::string path = cache_path();
     if (path.empty()) return;
-    const size_t slash = path.rfind('/');
-    if (slash != std::string::npos) {
-        const std::string dir = path.substr(0, slash);
-        std::string cmd = "mkdir -p '" + dir + "' 2>/dev/null";
-        if (dir.find('\'') == std::string::npos) (void)std::system(cmd.c_str());
-    }
+    const std::filesystem::path dir = std::filesystem::path(path).parent_path();
+    std::error_code ec;   // an unwritable cache only costs the tuning next time
+    if (!dir.empty()) std::filesystem::create_directories(dir, ec);
     std::ofstream f(path, std::ios::app);
     if (f) f << key << ' ' << shape[0] << ' ' << shape[1] << ' ' << shape[2] << '\n';
 }
@@ -918,7 +916,7 @@ int member_damping(hv_ens *e, int q, const double *nu_lat, const double *nu_top,
     return HV_OK;
 }
 
-// Time one kernel kind of one group for every tile shape; keep the fastest.
+// Time one kernel kind of one group in every launch configuration; keep the fastest.
 int tune(hv_ens *e, int32_t *out, int32_t *ngroups)
 {
     for (int q = 0; q < e->n; ++q)
@@ -941,9 +939,12 @@ int tune(hv_ens *e, int32_t *out, int32_t *ngroups)
     int rc = HV_OK;
     for (auto &g : e->groups) {
         for (int kind = 0; kind < NKIND && rc == HV_OK; ++kind) {
-            float best = 1e30f;
-            int best_s = g.shape[kind];
-            for (int s = 0; s < kConfigs && rc == HV_OK; ++s) {
+            // two interleaved rounds, the faster of each configuration's two
+            // timings counts (one round alone let run-to-run noise decide)
+            float t[kConfigs];
+            std::fill(t, t + kConfigs, 1e30f);
+            for (int it = 0; it < 2 * kConfigs && rc == HV_OK; ++it) {
+                const int s = it % kConfigs;
                 g.shape[kind] = s;
                 // the slow arrays the flux and short step read must hold this stage's values
                 if ((r = launch(g, KIND_PREP, e->stream)) != hipSuccess ||
@@ -957,9 +958,9 @@ int tune(hv_ens *e, int32_t *out, int32_t *ngroups)
                 float ms = 0.f;
                 if (r == hipSuccess) r = hipEventElapsedTime(&ms, a, b);
                 if (r != hipSuccess) { rc = hip_fail(e, r, "tune"); break; }
-                if (ms < best) { best = ms; best_s = s; }
+                t[s] = std::min(t[s], ms);
             }
-            g.shape[kind] = best_s;
+            g.shape[kind] = (int)(std::min_element(t, t + kConfigs) - t);
         }
         if (rc != HV_OK) break;
         cache_store(tune_key(e, g), g.shape);

@@ -1,5 +1,5 @@
 """GPU tests of the batched ensemble (hv_ens_*) and of the launch machinery
-shared with the single grid: hipGraph replay, autotuned tile shapes.
+shared with the single grid: hipGraph replay, autotuned launch configurations.
 
 Every cell's arithmetic is fixed, so the results must be bitwise identical
 whether a domain runs alone or inside an ensemble, with any tile shape, and

@@ -68,6 +68,9 @@ def _samples(s):
 def _check(hv, oracle, s, prec):
     print(f"case: full {s.name} {s.nx}x{s.ny}x{s.nz} {prec}: gpu step", flush=True)
     d = hv.Domain(s, precision=prec, layout="kij")
+    # the benchmark autotunes before it times; so does this run (the tuner
+    # leaves the state as it was)
+    print(f"case: full {s.name} {prec}: tuned launch configurations {d.tune()}", flush=True)
     d.step(s.dt, 1, s.n_short)
     got = d.read_all()
     m = d.mass()

@@ -69,7 +69,8 @@
  * against a dense LU; the assembled tridiagonal against the brute-force
  * Jacobian of the vertical update equations; and the horizontal and vertical
  * acoustic modes against their closed-form amplification matrices.
- * or_energy() is a diagnostic only: parity unpinned.
+ * or_energy() (a diagnostic): the closed-form energy of the isothermal rest
+ * state, flat and over terrain, and the kinetic increment of a uniform flow.
  *
  * Layout: canonical i-fastest, index i + nx*(j + ny*k); the vertical
  * momentum has nz+1 levels.  OpenMP parallelises over independent cells or
@@ -1042,7 +1043,9 @@ double or_mass(const or_grid *g, const double *rp)
 /* Diagnostic total energy: sum over cells of volume J dx dy dz times
  *   (1/2) [mean(U^2) + mean(V^2) + mean(W^2)] / rho + p/(gamma-1) + rho g z
  * with the means taken over the two faces of the cell and z the true height
- * of the cell centre.  Parity unpinned. */
+ * of the cell centre.  Pinned by the closed-form energy of the isothermal
+ * rest state (flat and over terrain) and by the kinetic increment of a
+ * uniform flow. */
 double or_energy(const or_grid *g, const double *const st[5])
 {
     const int nx = g->nx, ny = g->ny, nz = g->nz;

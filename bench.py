@@ -68,8 +68,9 @@ def kernel_digest() -> str:
 
 
 def read_traffic(prec: str):
-    """HBM bytes per short-step launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source; else None."""
+    """The committed rocprofv3 counter record of the short step (HBM bytes per
+    launch and the launch configuration it was taken in), if it was taken on
+    the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "short_step_large_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -80,7 +81,7 @@ def read_traffic(prec: str):
             except ValueError:
                 continue
             if rec.get("kernel_sha") == kernel_digest() and rec.get("precision") == prec:
-                return rec.get("bytes_per_launch")
+                return rec
     return None
 
 
@@ -304,6 +305,10 @@ def main():
                     help="lateral (8-cell) and upper (above 15 km) damping toward synthetic "
                          "boundary data after every short step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner: keep the launch configurations of the tune "
+                         "cache ($HV_TUNE_CACHE) or the defaults (the counter runs use this so "
+                         "that their passes measure one configuration)")
     ap.add_argument("--accuracy", action="store_true",
                     help="per-field error of every path against the float64 oracle on the "
                          "oracle-sized sub-run")
@@ -395,7 +400,7 @@ def main():
     res, finals = {}, {}
     for p in precs:
         r = time_precision(hevi, s, p, args.steps, args.warmup, args.layout, keep=keep,
-                           short=args.short)
+                           short=args.short, tune=not args.no_tune)
         if keep:
             r, finals[p] = r
         res[p] = r
@@ -410,11 +415,16 @@ def main():
     # twice per short step, the second reading 3 more fields)
     short_ms = r["kernels_ms_avg"]["short_step"]
     ach = short_step_bytes(b, s.cells) / (short_ms * 1e-3) / 1e9
-    traffic = read_traffic(primary)
+    rec = read_traffic(primary) if args.workload == "large" and args.short == "fb" and \
+        not args.damping and args.layout == "kij" else None
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": rec.get("bytes_per_launch") if rec else None,
                 "kernel": "short_step", "bytes_per_launch": short_step_bytes(b, s.cells),
                 "launch_ms_avg": round(short_ms, 4)}
+    if rec:
+        # the counters were taken with this tile x-extent (negative: XCD-banded)
+        roofline["traffic_tile_x"] = rec.get("tile_x")
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle baseline")

@@ -1509,7 +1509,9 @@ __device__ __forceinline__ void diffuse_body(const Lane<Lay, L> &ln, T kx, T ky,
     ln.load(q, 1, 0, e);
     ln.load(q, 0, -1, s);
     ln.load(q, 0, 1, n);
-    const T below = from_below(c[L - 1]), above = from_above(c[0]);
+    // shuffles, not DPP row shifts: measured 0.098 vs 0.114 ms per float32
+    // step on 1024x1024x64
+    const T below = from_below<SEG, false>(c[L - 1]), above = from_above<SEG, false>(c[0]);
     T r[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) {

@@ -97,3 +97,21 @@ def test_wind_reversing_with_height_matches_oracle(hv, oracle):
     got = _run(hv, s, "fp64", 3, s.n_short)
     for name, a, b in zip(inputs.FIELD_NAMES, got, ref):
         assert _rel(a, b) <= 1e-11, (name, _rel(a, b))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_unstable_run_reports_a_non_finite_mass(hv, prec):
+    """Failure detection: a short step far beyond the acoustic limit (c dtau /
+    dx ~ 100 with one short step per stage; the oracle refuses the first
+    column system, which is no longer diagonally dominant) grows by orders of
+    magnitude per long step and overflows well within 200 of them, in float64
+    too; the kernels keep running on the non-finite values, and hv_mass
+    reports HV_ERR_NONFINITE instead of a number."""
+    s = inputs.make_state(16, 16, 32, seed=77, noise=0.5, u_bg=5.0, n_short=1, dt=600.0)
+    print(f"case: unstable run {prec}", flush=True)
+    d = hv.Domain(s, precision=prec)
+    d.step(s.dt, 200, 1)
+    with pytest.raises(hv.HvError) as e:
+        d.mass()
+    assert e.value.code == hv.HV_ERR_NONFINITE
+    d.close()

@@ -284,14 +284,14 @@ __device__ __forceinline__ T from_above(T x) { return shift_down<1, SG, DPP>(x);
 // the bottom value is repeated (zero-gradient ghost); above it, either the top
 // value is repeated (cell quantities) or zero is used (level-face quantities,
 // whose face nz is the rigid lid).
-template <typename T, int L>
+template <int SG = SEG, typename T, int L>
 __device__ __forceinline__ void extend2(const T (&x)[L], T (&e)[L + 4], int p, bool zero_top)
 {
-    const T b2 = from_below(x[L - 2]);
-    const T b1 = from_below(x[L - 1]);
-    const T a0 = from_above(x[0]);
-    const T a1 = from_above(x[1]);
-    const bool bot = (p == 0), top = (p == SEG - 1);
+    const T b2 = from_below<SG>(x[L - 2]);
+    const T b1 = from_below<SG>(x[L - 1]);
+    const T a0 = from_above<SG>(x[0]);
+    const T a1 = from_above<SG>(x[1]);
+    const bool bot = (p == 0), top = (p == SG - 1);
     e[0] = bot ? x[0] : b2;
     e[1] = bot ? x[0] : b1;
 #pragma unroll
@@ -352,9 +352,9 @@ __device__ __forceinline__ T kface(T qLL, T qL, T qR, T qRR, T m)
 // --------------------------------------------------------------------------
 // slow sweep, part 1: specific velocities, theta and stage coefficients
 // --------------------------------------------------------------------------
-template <typename T, class Lay, int L, bool TR>
+template <typename T, class Lay, int L, bool TR, int SG>
 __device__ __forceinline__ void prep_body(
-    const Lane<Lay, L> &ln, const double *__restrict__ vm, const double *__restrict__ geo,
+    const Lane<Lay, L, SG> &ln, const double *__restrict__ vm, const double *__restrict__ geo,
     const T *__restrict__ rref3, const T *__restrict__ rtref3, const T *__restrict__ pref3,
     const T *__restrict__ rp, const T *__restrict__ U, const T *__restrict__ V,
     const T *__restrict__ W, const T *__restrict__ tp, T *__restrict__ uo, T *__restrict__ vo,
@@ -397,7 +397,7 @@ __device__ __forceinline__ void prep_body(
             rs[l] = rref[l] + rs[l];
         }
     }
-    const T rbelow = from_below(r0[L - 1]);
+    const T rbelow = from_below<SG>(r0[L - 1]);
     T u[L], v[L], w[L], th[L], P0[L], Cs[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) {
@@ -434,7 +434,7 @@ __device__ __forceinline__ void prep_body(
             mx[l] = T(0.5) * (su0 * Uc[l] + su1 * U1[l]);
             my[l] = T(0.5) * (sv0 * Vc[l] + sv1 * V1[l]);
         }
-        const T mxb = from_below(mx[L - 1]), myb = from_below(my[L - 1]);
+        const T mxb = from_below<SG>(mx[L - 1]), myb = from_below<SG>(my[L - 1]);
         T om[L];
 #pragma unroll
         for (int l = 0; l < L; ++l) {
@@ -448,14 +448,14 @@ __device__ __forceinline__ void prep_body(
     }
 }
 
-template <typename T, class Lay, int L, bool TR>
-__global__ __launch_bounds__(BLOCK) void k_slow_prep(Group gr)
+template <typename T, class Lay, int L, bool TR, int SG>
+__global__ __launch_bounds__(kColsPerBlock * SG) void k_slow_prep(Group gr)
 {
-    const Where wh = locate(gr);
+    const Where wh = locate<SG>(gr);
     if (!wh.active) return;
     const MemberDev *m = wh.m;
-    const Lane<Lay, L> ln(m->nx, m->ny, m->nz, wh.i, wh.j);
-    prep_body<T, Lay, L, TR>(ln, m->vm, m->geo, (const T *)m->ref[0], (const T *)m->ref[1],
+    const Lane<Lay, L, SG> ln(m->nx, m->ny, m->nz, wh.i, wh.j);
+    prep_body<T, Lay, L, TR, SG>(ln, m->vm, m->geo, (const T *)m->ref[0], (const T *)m->ref[1],
                              (const T *)m->ref[2], (const T *)buf(m, gr.src, 0),
                              (const T *)buf(m, gr.src, 1), (const T *)buf(m, gr.src, 2),
                              (const T *)buf(m, gr.src, 3), (const T *)buf(m, gr.src, 4),
@@ -470,8 +470,8 @@ __global__ __launch_bounds__(BLOCK) void k_slow_prep(Group gr)
 // the momentum control volumes take means of the cell-face fluxes, the
 // vertical mass flux is Omega (Wz = Omega, else Wz = W) and each tendency is
 // divided by the Jacobian of its control volume.
-template <typename T, class Lay, int L, bool TR>
-__device__ __forceinline__ void slow_su(const Lane<Lay, L> &ln, T rdx, T rdy, const T (&rdz)[L],
+template <typename T, class Lay, int L, bool TR, int SG>
+__device__ __forceinline__ void slow_su(const Lane<Lay, L, SG> &ln, T rdx, T rdy, const T (&rdz)[L],
                                         const double *__restrict__ geo, const T *__restrict__ U,
                                         const T *__restrict__ V, const T *__restrict__ Wz,
                                         const T *__restrict__ uu, T *__restrict__ SU)
@@ -504,8 +504,8 @@ __device__ __forceinline__ void slow_su(const Lane<Lay, L> &ln, T rdx, T rdy, co
         jv01 = (T)ln.geo(geo, GEO_JV, 0, 1);
     }
     T ue[L + 4];
-    extend2(ux[2], ue, ln.p, false);
-    const bool top = (ln.p == SEG - 1);
+    extend2<SG>(ux[2], ue, ln.p, false);
+    const bool top = (ln.p == SG - 1);
     // fluxes through the lane's level faces k0 .. k0+L-1; face k0+L is the
     // first face of the lane above (the rigid lid for the top lane)
     T fz[L + 1];
@@ -515,7 +515,7 @@ __device__ __forceinline__ void slow_su(const Lane<Lay, L> &ln, T rdx, T rdy, co
         const T q = kface(ue[l], ue[l + 1], ue[l + 2], ue[l + 3], m);
         fz[l] = (ln.k0 + l == 0) ? T(0) : m * q;
     }
-    const T fz_a = from_above(fz[0]);
+    const T fz_a = from_above<SG>(fz[0]);
     fz[L] = top ? T(0) : fz_a;
     T out[L];
 #pragma unroll
@@ -543,8 +543,8 @@ __device__ __forceinline__ void slow_su(const Lane<Lay, L> &ln, T rdx, T rdy, co
     ln.store(SU, out);
 }
 
-template <typename T, class Lay, int L, bool TR>
-__device__ __forceinline__ void slow_sv(const Lane<Lay, L> &ln, T rdx, T rdy, const T (&rdz)[L],
+template <typename T, class Lay, int L, bool TR, int SG>
+__device__ __forceinline__ void slow_sv(const Lane<Lay, L, SG> &ln, T rdx, T rdy, const T (&rdz)[L],
                                         const double *__restrict__ geo, const T *__restrict__ U,
                                         const T *__restrict__ V, const T *__restrict__ Wz,
                                         const T *__restrict__ vv, T *__restrict__ SV)
@@ -577,8 +577,8 @@ __device__ __forceinline__ void slow_sv(const Lane<Lay, L> &ln, T rdx, T rdy, co
         ju10 = (T)ln.geo(geo, GEO_JU, 1, 0);
     }
     T ve[L + 4];
-    extend2(vy[2], ve, ln.p, false);
-    const bool top = (ln.p == SEG - 1);
+    extend2<SG>(vy[2], ve, ln.p, false);
+    const bool top = (ln.p == SG - 1);
     // fluxes through the lane's level faces k0 .. k0+L-1; face k0+L is the
     // first face of the lane above (the rigid lid for the top lane)
     T fz[L + 1];
@@ -588,7 +588,7 @@ __device__ __forceinline__ void slow_sv(const Lane<Lay, L> &ln, T rdx, T rdy, co
         const T q = kface(ve[l], ve[l + 1], ve[l + 2], ve[l + 3], m);
         fz[l] = (ln.k0 + l == 0) ? T(0) : m * q;
     }
-    const T fz_a = from_above(fz[0]);
+    const T fz_a = from_above<SG>(fz[0]);
     fz[L] = top ? T(0) : fz_a;
     T out[L];
 #pragma unroll
@@ -616,8 +616,8 @@ __device__ __forceinline__ void slow_sv(const Lane<Lay, L> &ln, T rdx, T rdy, co
     ln.store(SV, out);
 }
 
-template <typename T, class Lay, int L, bool TR>
-__device__ __forceinline__ void slow_sw(const Lane<Lay, L> &ln, T rdx, T rdy,
+template <typename T, class Lay, int L, bool TR, int SG>
+__device__ __forceinline__ void slow_sw(const Lane<Lay, L, SG> &ln, T rdx, T rdy,
                                         const double *__restrict__ vm, const double *__restrict__ geo,
                                         const T *__restrict__ U, const T *__restrict__ V,
                                         const T *__restrict__ Wz, const T *__restrict__ ww,
@@ -637,11 +637,11 @@ __device__ __forceinline__ void slow_sw(const Lane<Lay, L> &ln, T rdx, T rdy,
     ln.load(V, 0, 1, V1);
     ln.load(Wz, 0, 0, W0);
     // level below the lane's first level (unused on the bottom level face)
-    const T U0b = from_below(U0[L - 1]), U1b = from_below(U1[L - 1]);
-    const T V0b = from_below(V0[L - 1]), V1b = from_below(V1[L - 1]);
+    const T U0b = from_below<SG>(U0[L - 1]), U1b = from_below<SG>(U1[L - 1]);
+    const T V0b = from_below<SG>(V0[L - 1]), V1b = from_below<SG>(V1[L - 1]);
     T we[L + 4], We[L + 4];
-    extend2(wx[2], we, ln.p, true);
-    extend2(W0, We, ln.p, true);
+    extend2<SG>(wx[2], we, ln.p, true);
+    extend2<SG>(W0, We, ln.p, true);
     T rdzf[L];
     ln.vmet(vm, VM_RDZF, rdzf);
     T ju0 = T(1), ju1 = T(1), jv0 = T(1), jv1 = T(1), jc = T(1);
@@ -661,7 +661,7 @@ __device__ __forceinline__ void slow_sw(const Lane<Lay, L> &ln, T rdx, T rdy,
         const T m = T(0.5) * (We[l + 1] + We[l + 2]);
         fz[l] = m * kface(we[l], we[l + 1], we[l + 2], we[l + 3], m);
     }
-    fz[0] = from_below(fz[L]);
+    fz[0] = from_below<SG>(fz[L]);
     T out[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) {
@@ -695,8 +695,8 @@ __device__ __forceinline__ void slow_sw(const Lane<Lay, L> &ln, T rdx, T rdy,
     ln.store(SW, out);
 }
 
-template <typename T, class Lay, int L, bool TR>
-__device__ __forceinline__ void slow_rt(const Lane<Lay, L> &ln, T rdx, T rdy, const T (&rdz)[L],
+template <typename T, class Lay, int L, bool TR, int SG>
+__device__ __forceinline__ void slow_rt(const Lane<Lay, L, SG> &ln, T rdx, T rdy, const T (&rdz)[L],
                                         const double *__restrict__ vm, const double *__restrict__ geo,
                                         const T *__restrict__ U, const T *__restrict__ V,
                                         const T *__restrict__ Wz, const T *__restrict__ th,
@@ -724,8 +724,8 @@ __device__ __forceinline__ void slow_rt(const Lane<Lay, L> &ln, T rdx, T rdy, co
         jc = (T)ln.geo(geo, GEO_J, 0, 0);
     }
     T te[L + 4];
-    extend2(tx[2], te, ln.p, false);
-    const bool top = (ln.p == SEG - 1);
+    extend2<SG>(tx[2], te, ln.p, false);
+    const bool top = (ln.p == SG - 1);
     T a[L], b[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) {
@@ -742,7 +742,7 @@ __device__ __forceinline__ void slow_rt(const Lane<Lay, L> &ln, T rdx, T rdy, co
         const T tcen = a[l] * te[l + 2] + b[l] * te[l + 1];
         gz[l] = (ln.k0 + l == 0) ? T(0) : m * (tl - tcen);
     }
-    const T gz_a = from_above(gz[0]);
+    const T gz_a = from_above<SG>(gz[0]);
     gz[L] = top ? T(0) : gz_a;
     T out[L];
 #pragma unroll
@@ -769,9 +769,9 @@ __device__ __forceinline__ void slow_rt(const Lane<Lay, L> &ln, T rdx, T rdy, co
     ln.store(RT, out);
 }
 
-template <typename T, class Lay, int L, bool TR>
+template <typename T, class Lay, int L, bool TR, int SG>
 __device__ __forceinline__ void flux_body(
-    const Lane<Lay, L> &ln, const double *__restrict__ vm, const double *__restrict__ geo, T rdx,
+    const Lane<Lay, L, SG> &ln, const double *__restrict__ vm, const double *__restrict__ geo, T rdx,
     T rdy, const T *__restrict__ U, const T *__restrict__ V, const T *__restrict__ Wz,
     const T *__restrict__ uu, const T *__restrict__ vv, const T *__restrict__ ww,
     const T *__restrict__ th, T *__restrict__ SU, T *__restrict__ SV, T *__restrict__ SW,
@@ -779,10 +779,10 @@ __device__ __forceinline__ void flux_body(
 {
     T rdz[L];
     ln.vmet(vm, VM_RDZ, rdz);
-    slow_su<T, Lay, L, TR>(ln, rdx, rdy, rdz, geo, U, V, Wz, uu, SU);
-    slow_sv<T, Lay, L, TR>(ln, rdx, rdy, rdz, geo, U, V, Wz, vv, SV);
-    slow_sw<T, Lay, L, TR>(ln, rdx, rdy, vm, geo, U, V, Wz, ww, SW);
-    slow_rt<T, Lay, L, TR>(ln, rdx, rdy, rdz, vm, geo, U, V, Wz, th, RT);
+    slow_su<T, Lay, L, TR, SG>(ln, rdx, rdy, rdz, geo, U, V, Wz, uu, SU);
+    slow_sv<T, Lay, L, TR, SG>(ln, rdx, rdy, rdz, geo, U, V, Wz, vv, SV);
+    slow_sw<T, Lay, L, TR, SG>(ln, rdx, rdy, vm, geo, U, V, Wz, ww, SW);
+    slow_rt<T, Lay, L, TR, SG>(ln, rdx, rdy, rdz, vm, geo, U, V, Wz, th, RT);
 }
 
 // The flat float32 flux kernel with 4 contiguous levels per lane fits 4 waves
@@ -792,15 +792,16 @@ __device__ __forceinline__ void flux_body(
 template <typename T, class Lay, int L, bool TR>
 constexpr int flux_waves() { return (sizeof(T) == 4 && L == 4 && !TR && Lay::kContig) ? 4 : 1; }
 
-template <typename T, class Lay, int L, bool TR>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(flux_waves<T, Lay, L, TR>())))
+template <typename T, class Lay, int L, bool TR, int SG>
+__global__ __launch_bounds__(kColsPerBlock * SG)
+__attribute__((amdgpu_waves_per_eu(flux_waves<T, Lay, L, TR>())))
 void k_slow_flux(Group gr)
 {
-    const Where wh = locate(gr);
+    const Where wh = locate<SG>(gr);
     if (!wh.active) return;
     const MemberDev *m = wh.m;
-    const Lane<Lay, L> ln(m->nx, m->ny, m->nz, wh.i, wh.j);
-    flux_body<T, Lay, L, TR>(ln, m->vm, m->geo, (T)m->rdx, (T)m->rdy, (const T *)buf(m, gr.src, 1),
+    const Lane<Lay, L, SG> ln(m->nx, m->ny, m->nz, wh.i, wh.j);
+    flux_body<T, Lay, L, TR, SG>(ln, m->vm, m->geo, (T)m->rdx, (T)m->rdy, (const T *)buf(m, gr.src, 1),
                              (const T *)buf(m, gr.src, 2),
                              TR ? (const T *)m->spec[3] : (const T *)buf(m, gr.src, 3),
                              (const T *)m->spec[0], (const T *)m->spec[1], (const T *)m->spec[2],
@@ -1566,27 +1567,41 @@ hipError_t dispatch(int prec, int layout, int L, Args &&...args)
     }
 }
 
+// The float64 prep with 4 levels per lane runs in 32-lane segments, as the
+// flux does.
 template <typename T, typename S, class Lay, int L>
 struct RunPrep {
+    static constexpr bool kWide = sizeof(T) == 8 && L == 4;
+    static constexpr int kSG = kWide ? 2 * SEG : SEG;
+    static constexpr int kL = kWide ? L / 2 : L;
     static hipError_t run(const Group &gr, hipStream_t s)
     {
         if (gr.terrain)
-            hipLaunchKernelGGL((k_slow_prep<T, Lay, L, true>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr);
+            hipLaunchKernelGGL((k_slow_prep<T, Lay, kL, true, kSG>), dim3(gr.nblocks), dim3(kColsPerBlock * kSG),
+                               0, s, gr);
         else
-            hipLaunchKernelGGL((k_slow_prep<T, Lay, L, false>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr);
+            hipLaunchKernelGGL((k_slow_prep<T, Lay, kL, false, kSG>), dim3(gr.nblocks), dim3(kColsPerBlock * kSG),
+                               0, s, gr);
         return hipGetLastError();
     }
 };
 
+// The float64 flux with 4 levels per lane runs in 32-lane segments (2
+// levels per lane: half the registers per lane, higher occupancy).
 template <typename T, typename S, class Lay, int L>
 struct RunFlux {
+    static constexpr bool kWide = sizeof(T) == 8 && L == 4;
+    static constexpr int kSG = kWide ? 2 * SEG : SEG;
+    static constexpr int kL = kWide ? L / 2 : L;
     template <class A>
     static void go(const Group &gr, hipStream_t s)
     {
         if (gr.terrain)
-            hipLaunchKernelGGL((k_slow_flux<T, A, L, true>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr);
+            hipLaunchKernelGGL((k_slow_flux<T, A, kL, true, kSG>), dim3(gr.nblocks), dim3(kColsPerBlock * kSG),
+                               0, s, gr);
         else
-            hipLaunchKernelGGL((k_slow_flux<T, A, L, false>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr);
+            hipLaunchKernelGGL((k_slow_flux<T, A, kL, false, kSG>), dim3(gr.nblocks), dim3(kColsPerBlock * kSG),
+                               0, s, gr);
     }
     // The slow flux is instruction-heavy enough that 32-bit array offsets pay
     // (float32: 0.973 -> 0.895 ms, float64: 2.50 -> 2.09 ms on 1024x1024x64);

@@ -61,7 +61,7 @@ enum {
     HV_ERR_HIP = -2,          /* a HIP runtime call failed (see hv_last_error)*/
     HV_ERR_STATE = -3,        /* step/read/mass before hv_state_init          */
     HV_ERR_NONFINITE = -4,    /* the FP64 mass sum is not finite              */
-    HV_ERR_UNSUPPORTED = -5   /* valid request this build does not implement  */
+    HV_ERR_UNSUPPORTED = -5   /* valid request the library does not implement */
 };
 
 /* Arithmetic of the stencil sweeps / of the column solve and global sums:

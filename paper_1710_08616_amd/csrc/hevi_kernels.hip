@@ -1,20 +1,22 @@
 // hevi_kernels.hip -- HIP kernels of the HEVI dynamical-core step for gfx950.
 //
 // Work mapping.  A column (i, j) of nz cells is owned by one 16-lane segment
-// of a 64-lane wavefront; lane p of the segment owns the L = nz/16 consecutive
-// levels k0 = p*L .. k0+L-1.  In the column-fastest layout those L values are
+// of a 64-lane wavefront (32 lanes for float64 storage with 64 levels); lane p
+// of the segment owns the L = nz/16 (nz/32) consecutive levels
+// k0 = p*L .. k0+L-1.  In the column-fastest layout those L values are
 // contiguous, so each per-lane access is one vector load and a wavefront
-// touches 4 columns of contiguous memory.  Vertical neighbours live in the
-// adjacent lane of the same segment (segment shuffles); horizontal neighbours
-// are other columns and come through L1/L2.  A block of 256 threads covers a
-// tile of 16 columns (16x1, 8x2 or 4x4, in launch or XCD-banded order, as the
+// touches 4 (2) columns of contiguous memory.  Vertical neighbours live in the
+// adjacent lane of the same segment (DPP row shifts or shuffles); horizontal
+// neighbours are other columns and come through L1/L2.  A block covers a tile
+// of 16 columns (16x1, 8x2 or 4x4, in launch or XCD-banded order, as the
 // autotuner chose; the results do not depend on it).
 //
 // The per-column tridiagonal system of the vertically implicit part is solved
 // without leaving the segment: every lane eliminates its interior rows in
 // terms of the last unknown of the lane below and its own last unknown; the
-// remaining 16-row system of those interface unknowns is solved by parallel
-// cyclic reduction over the segment (4 steps), and the interior values follow.
+// remaining 16-row (32-row) system of those interface unknowns is solved by
+// parallel cyclic reduction over the segment (4 or 5 steps), and the interior
+// values follow.
 //
 // Equations: the paper (Sect. 1.1) fixes finite volumes, an RK3 long step
 // after Wicker & Skamarock (2002) and HEVI short steps; the discrete form

@@ -28,6 +28,7 @@
 #include <new>
 #include <sstream>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "hevi_kernels.h"
@@ -246,22 +247,74 @@ inline size_t dev_index(int layout, const MemberHost &m, int i, int j, int k)
     return ((size_t)k * m.ny + j) * m.nx + i;
 }
 
+// body(j0, j1) over rows [0, n) of per_row elements each, split between up
+// to 16 host threads when there are more than 2^20 elements (serial if
+// threads cannot be started); every element is written by one thread.
+template <typename F>
+void parallel_rows(int n, size_t per_row, F &&body)
+{
+    unsigned nt = std::thread::hardware_concurrency();
+    nt = std::max(1u, std::min(nt, 16u));
+    nt = std::min(nt, (unsigned)std::max(n, 1));
+    if (nt > 1 && (size_t)n * per_row > (size_t(1) << 20)) {
+        std::vector<std::thread> th;
+        try {
+            for (unsigned t = 1; t < nt; ++t)
+                th.emplace_back([&, t] { body((int)((size_t)n * t / nt), (int)((size_t)n * (t + 1) / nt)); });
+        } catch (...) {
+            for (auto &x : th) x.join();
+            body(0, n);   // idempotent: plain element copies
+            return;
+        }
+        body(0, (int)((size_t)n / nt));
+        for (auto &x : th) x.join();
+        return;
+    }
+    body(0, n);
+}
+
+// Canonical i-fastest <-> device order.  For the column-fastest order each
+// row j is a transpose of an nz x nx block, done in 32 x 32 tiles.
+template <typename S, typename D>
+void reorder(int layout, const MemberHost &m, const S *src, D *dst, bool to_device)
+{
+    const int nx = m.nx, ny = m.ny, nz = m.nz;
+    parallel_rows(ny, (size_t)nx * nz, [&](int j0, int j1) {
+        for (int j = j0; j < j1; ++j) {
+            if (layout != HV_KIJ) {
+                for (int k = 0; k < nz; ++k) {
+                    const size_t o = canon(0, j, k, nx, ny);
+                    for (int i = 0; i < nx; ++i) dst[o + i] = (D)src[o + i];
+                }
+                continue;
+            }
+            for (int i0 = 0; i0 < nx; i0 += 32)
+                for (int k0 = 0; k0 < nz; k0 += 32) {
+                    const int i1 = std::min(nx, i0 + 32), k1 = std::min(nz, k0 + 32);
+                    if (to_device) {
+                        for (int i = i0; i < i1; ++i)
+                            for (int k = k0; k < k1; ++k)
+                                dst[dev_index(layout, m, i, j, k)] = (D)src[canon(i, j, k, nx, ny)];
+                    } else {
+                        for (int k = k0; k < k1; ++k)
+                            for (int i = i0; i < i1; ++i)
+                                dst[canon(i, j, k, nx, ny)] = (D)src[dev_index(layout, m, i, j, k)];
+                    }
+                }
+        }
+    });
+}
+
 template <typename T>
 void to_device_order(int layout, const MemberHost &m, const double *src, T *dst)
 {
-    for (int k = 0; k < m.nz; ++k)
-        for (int j = 0; j < m.ny; ++j)
-            for (int i = 0; i < m.nx; ++i)
-                dst[dev_index(layout, m, i, j, k)] = (T)src[canon(i, j, k, m.nx, m.ny)];
+    reorder(layout, m, src, dst, true);
 }
 
 template <typename T>
 void from_device_order(int layout, const MemberHost &m, const T *src, double *dst)
 {
-    for (int k = 0; k < m.nz; ++k)
-        for (int j = 0; j < m.ny; ++j)
-            for (int i = 0; i < m.nx; ++i)
-                dst[canon(i, j, k, m.nx, m.ny)] = (double)src[dev_index(layout, m, i, j, k)];
+    reorder(layout, m, src, dst, false);
 }
 
 // Per-level table; rho, rt, p are the reference columns (NULL over terrain,
@@ -669,9 +722,15 @@ int member_init(hv_ens *e, int q, const double *const fields[5], const double *r
             !(p_ref[k] > 0) || !std::isfinite(rhotheta_ref[k]) || !(rhotheta_ref[k] > 0))
             return fail(e, HV_ERR_ARG, "reference values must be finite and positive");
     for (int f = 0; f < 5; ++f) {
-        const size_t cnt = (f == HV_RHOW ? nxy * (m.nz + 1) : nxy * m.nz);
-        for (size_t c = 0; c < cnt; ++c)
-            if (!std::isfinite(fields[f][c])) return fail(e, HV_ERR_ARG, "non-finite value in a field");
+        const int levels = f == HV_RHOW ? m.nz + 1 : m.nz;
+        std::vector<char> bad(levels, 0);
+        parallel_rows(levels, nxy, [&](int k0, int k1) {
+            for (int k = k0; k < k1; ++k)
+                for (size_t c = 0; c < nxy; ++c)
+                    if (!std::isfinite(fields[f][(size_t)k * nxy + c])) { bad[k] = 1; break; }
+        });
+        for (char b : bad)
+            if (b) return fail(e, HV_ERR_ARG, "non-finite value in a field");
     }
     for (size_t c = 0; c < nxy; ++c)
         if (fields[HV_RHOW][c] != 0.0 || fields[HV_RHOW][nxy * m.nz + c] != 0.0)

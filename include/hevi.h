@@ -168,7 +168,8 @@ int hv_trace_read(hv_grid_t g, int32_t kind, double *ms_total, int64_t *launches
  * P tiles and shares its L2 between neighbours).  The choice is appended to
  * a plain-text cache ($HV_TUNE_CACHE, else $HOME/.cache/hevi/tune.txt; one
  * line "key c_prep c_flux c_short", c = shape index 0..2 for 16x1, 8x2, 4x4,
- * plus 3 for the XCD-banded order; the last line of a key wins) that later
+ * plus 3 for the XCD-banded order; the last line of a key wins, and hv_tune
+ * rewrites the file with one line per key) that later
  * grids of the same kind read at creation.  tile_x_out (may be NULL)
  * receives the chosen x-extent of the three kinds, negated for the
  * XCD-banded order.  Synchronises the stream; does not change the state.

@@ -25,6 +25,7 @@
 #include <cstring>
 #include <filesystem>
 #include <fstream>
+#include <functional>
 #include <new>
 #include <sstream>
 #include <string>
@@ -559,6 +560,8 @@ bool cache_lookup(const std::string &key, int shape[NKIND])
     return found;
 }
 
+// Replaces the key's line (the file keeps one line per key); written to a
+// temporary file and renamed, so a reader never sees a partial file.
 void cache_store(const std::string &key, const int shape[NKIND])
 {
     const std::string path = cache_path();
@@ -566,8 +569,26 @@ void cache_store(const std::string &key, const int shape[NKIND])
     const std::filesystem::path dir = std::filesystem::path(path).parent_path();
     std::error_code ec;   // an unwritable cache only costs the tuning next time
     if (!dir.empty()) std::filesystem::create_directories(dir, ec);
-    std::ofstream f(path, std::ios::app);
-    if (f) f << key << ' ' << shape[0] << ' ' << shape[1] << ' ' << shape[2] << '\n';
+    std::vector<std::string> keep;
+    {
+        std::ifstream in(path);
+        std::string line;
+        while (std::getline(in, line)) {
+            std::istringstream ls(line);
+            std::string k;
+            if ((ls >> k) && k != key) keep.push_back(line);
+        }
+    }
+    const std::string tmp = path + ".tmp" + std::to_string((unsigned long)std::hash<std::string>{}(key) & 0xFFFFu);
+    {
+        std::ofstream out(tmp, std::ios::trunc);
+        if (!out) return;
+        for (const auto &l : keep) out << l << '\n';
+        out << key << ' ' << shape[0] << ' ' << shape[1] << ' ' << shape[2] << '\n';
+        if (!out) return;
+    }
+    std::filesystem::rename(tmp, path, ec);
+    if (ec) std::filesystem::remove(tmp, ec);
 }
 
 // ---- creation ----

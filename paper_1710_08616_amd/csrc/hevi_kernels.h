@@ -12,7 +12,10 @@ constexpr int kBlock = 256;            // threads per block
 constexpr int kColsPerBlock = kBlock / kSeg;
 constexpr int kMaxPartials = 1024;     // mass-sum partials per member
 
-// Per-level constant table (float64), entry f*nz + k.
+// Per-level constant table: VM_NFIELDS * nz float64 values, entry f*nz + k,
+// followed by the same values rounded to float32 in the same order (float
+// kernels read that copy: half the registers and load instructions, and the
+// same values they would get by converting).
 enum VmField {
     VM_DZ = 0,     // cell thickness dz_k
     VM_RDZ,        // 1/dz_k
@@ -29,6 +32,11 @@ enum VmField {
     VM_DF,         // 1 - zeta/H at level face k
     VM_NFIELDS
 };
+
+inline constexpr size_t vm_bytes(int nz)
+{
+    return (sizeof(double) + sizeof(float)) * (size_t)VM_NFIELDS * (size_t)nz;
+}
 
 // Per-column geometry of a terrain-following grid (float64, 8 per column,
 // column-major i-fastest): Jacobians and slopes of z = zeta + h (1 - zeta/H).

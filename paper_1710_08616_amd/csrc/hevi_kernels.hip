@@ -224,15 +224,34 @@ struct Lane {
     {
         return g[((size_t)wrapc(j + dj, ny) * nx + wrapc(i + di, nx)) * GEO_NFIELDS + f];
     }
-    // per-level constant of the lane's levels (+ offset), as type S
-    template <typename S>
+    // per-level constant of the lane's levels (+ offset, clamped to the
+    // column), as type S; float reads the table's float32 copy (the lane's
+    // own L levels as one vector) unless F32 is false
+    template <typename S, bool F32 = true>
     __device__ void vmet(const double *__restrict__ vm, int f, S (&x)[L], int koff = 0) const
     {
+        if constexpr (F32 && sizeof(S) == sizeof(float)) {
+            const float *__restrict__ vf = (const float *)(vm + (size_t)VM_NFIELDS * nz) +
+                                           (size_t)f * nz;
+            if (koff == 0) {
+                const vec_t<float, L> t = *(const vec_t<float, L> *)(vf + k0);
 #pragma unroll
-        for (int l = 0; l < L; ++l) {
-            int k = k0 + l + koff;
-            k = k < 0 ? 0 : (k >= nz ? nz - 1 : k);
-            x[l] = (S)vm[(size_t)f * nz + k];
+                for (int l = 0; l < L; ++l) x[l] = t[l];
+                return;
+            }
+#pragma unroll
+            for (int l = 0; l < L; ++l) {
+                int k = k0 + l + koff;
+                k = k < 0 ? 0 : (k >= nz ? nz - 1 : k);
+                x[l] = vf[k];
+            }
+        } else {
+#pragma unroll
+            for (int l = 0; l < L; ++l) {
+                int k = k0 + l + koff;
+                k = k < 0 ? 0 : (k >= nz ? nz - 1 : k);
+                x[l] = (S)vm[(size_t)f * nz + k];
+            }
         }
     }
 };
@@ -645,7 +664,7 @@ __device__ __forceinline__ void slow_sw(const Lane<Lay, L, SG> &ln, T rdx, T rdy
     extend2<SG>(wx[2], we, ln.p, true);
     extend2<SG>(W0, We, ln.p, true);
     T rdzf[L];
-    ln.vmet(vm, VM_RDZF, rdzf);
+    ln.template vmet<T, TR>(vm, VM_RDZF, rdzf);
     T ju0 = T(1), ju1 = T(1), jv0 = T(1), jv1 = T(1), jc = T(1);
     if constexpr (TR) {
         ju0 = (T)ln.geo(geo, GEO_JU, 0, 0);
@@ -728,11 +747,18 @@ __device__ __forceinline__ void slow_rt(const Lane<Lay, L, SG> &ln, T rdx, T rdy
     T te[L + 4];
     extend2<SG>(tx[2], te, ln.p, false);
     const bool top = (ln.p == SG - 1);
+    // the flat slow flux reads the float64 table (measured: the float32 copy
+    // changes its schedule and costs 7% there, while it saves 8% over terrain)
     T a[L], b[L];
+    if constexpr (TR) {
+        ln.vmet(vm, VM_A, a);
+        ln.vmet(vm, VM_B, b);
+    } else {
 #pragma unroll
-    for (int l = 0; l < L; ++l) {
-        a[l] = (T)vm[(size_t)VM_A * ln.nz + ln.k0 + l];
-        b[l] = (T)vm[(size_t)VM_B * ln.nz + ln.k0 + l];
+        for (int l = 0; l < L; ++l) {
+            a[l] = (T)vm[(size_t)VM_A * ln.nz + ln.k0 + l];
+            b[l] = (T)vm[(size_t)VM_B * ln.nz + ln.k0 + l];
+        }
     }
     // fluxes through the lane's level faces k0 .. k0+L-1; face k0+L is the
     // first face of the lane above (the rigid lid for the top lane)
@@ -780,7 +806,7 @@ __device__ __forceinline__ void flux_body(
     T *__restrict__ RT)
 {
     T rdz[L];
-    ln.vmet(vm, VM_RDZ, rdz);
+    ln.template vmet<T, TR>(vm, VM_RDZ, rdz);
     slow_su<T, Lay, L, TR, SG>(ln, rdx, rdy, rdz, geo, U, V, Wz, uu, SU);
     slow_sv<T, Lay, L, TR, SG>(ln, rdx, rdy, rdz, geo, U, V, Wz, vv, SV);
     slow_sw<T, Lay, L, TR, SG>(ln, rdx, rdy, vm, geo, U, V, Wz, ww, SW);
@@ -1628,11 +1654,26 @@ struct RunShort {
     static constexpr bool kWide = sizeof(T) == 8 && L == 4;
     static constexpr int kSG = kWide ? 2 * SEG : SEG;
     static constexpr int kL = kWide ? L / 2 : L;
+    template <class A, bool TR, bool EV, bool DP>
+    static void launch(const Group &gr, double frac, double offset, hipStream_t s)
+    {
+        hipLaunchKernelGGL((k_short_step<T, S, A, kL, TR, EV, kSG, DP>), dim3(gr.nblocks),
+                           dim3(kColsPerBlock * kSG), 0, s, gr, frac, offset);
+    }
+    // 32-bit offsets with global instructions pay in the flat, undamped
+    // float32 step only (measured on 1024 x 1024 x 64: 0.895 -> 0.876 ms;
+    // the Runge-Kutta pair unchanged; the float64-solve form loses 4%, the
+    // terrain form 5%, the damped form 4%)
     template <bool TR, bool EV, bool DP>
     static void go(const Group &gr, double frac, double offset, hipStream_t s)
     {
-        hipLaunchKernelGGL((k_short_step<T, S, Lay, kL, TR, EV, kSG, DP>), dim3(gr.nblocks),
-                           dim3(kColsPerBlock * kSG), 0, s, gr, frac, offset);
+        if constexpr (std::is_same_v<S, float> && !TR && !DP) {
+            if (gr.off32) {
+                launch<Off32<Lay, true>, TR, EV, DP>(gr, frac, offset, s);
+                return;
+            }
+        }
+        launch<Lay, TR, EV, DP>(gr, frac, offset, s);
     }
     template <bool TR, bool EV>
     static void go2(const Group &gr, double frac, double offset, hipStream_t s)

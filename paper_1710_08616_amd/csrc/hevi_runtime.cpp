@@ -231,7 +231,7 @@ Plan make_plan(int n, const hv_grid_desc *d)
             for (int a = 0; a < 4; ++a) c.take(ncell * es);
             c.take(sizeof(double) * hv::GEO_NFIELDS * (size_t)d[q].nx * d[q].ny);
         }
-        c.take(sizeof(double) * hv::VM_NFIELDS * d[q].nz);
+        c.take(hv::vm_bytes(d[q].nz));
         c.take(sizeof(double) * (size_t)hv::partials_of(d[q].nx, d[q].ny));
         c.take(sizeof(double) * 4);
         p.member_off.push_back(start);
@@ -665,7 +665,7 @@ int ens_create(hv_ens *e, int n, const hv_grid_desc *descs, void *ws, size_t byt
             if (r == hipSuccess) r = sync(e);
             if (r != hipSuccess) return hip_fail(nullptr, r, "upload geometry");
         }
-        v.vm = (const double *)(base + c.take(sizeof(double) * hv::VM_NFIELDS * m.nz));
+        v.vm = (const double *)(base + c.take(hv::vm_bytes(m.nz)));
         v.partials = (double *)(base + c.take(sizeof(double) * (size_t)v.npart));
         v.sums = (double *)(base + c.take(sizeof(double) * 4));
     }
@@ -761,7 +761,11 @@ int member_init(hv_ens *e, int q, const double *const fields[5], const double *r
     std::vector<double> vm;
     if (terrain) fill_vmet(m, nullptr, nullptr, nullptr, vm);
     else fill_vmet(m, rho_ref, rhotheta_ref, p_ref, vm);
-    r = hipMemcpy((void *)m.dev.vm, vm.data(), vm.size() * sizeof(double), hipMemcpyHostToDevice);
+    std::vector<unsigned char> vmb(hv::vm_bytes(m.nz));
+    std::memcpy(vmb.data(), vm.data(), vm.size() * sizeof(double));
+    float *vmf = (float *)(vmb.data() + vm.size() * sizeof(double));
+    for (size_t q = 0; q < vm.size(); ++q) vmf[q] = (float)vm[q];
+    r = hipMemcpy((void *)m.dev.vm, vmb.data(), vmb.size(), hipMemcpyHostToDevice);
     if (r != hipSuccess) return hip_fail(e, r, "hipMemcpy(vmet)");
     std::vector<double> bd;
     std::vector<float> bf;

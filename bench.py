@@ -423,7 +423,7 @@ def main():
                 "kernel": "short_step", "bytes_per_launch": short_step_bytes(b, s.cells),
                 "launch_ms_avg": round(short_ms, 4)}
     if rec:
-        # the counters were taken with this tile x-extent (negative: XCD-banded)
+        # the counters were taken with this tile x-extent (negative: XCD-chunked)
         roofline["traffic_tile_x"] = rec.get("tile_x")
     cpu = None
     if not args.no_cpu_baseline:

@@ -163,16 +163,16 @@ int hv_trace_read(hv_grid_t g, int32_t kind, double *ms_total, int64_t *launches
  * loaded state with every launch configuration and keep the fastest; results
  * are bitwise independent of the configuration.  A configuration is a tile
  * shape (16x1, 8x2, 4x4 columns of a 256-thread block) and a block order:
- * launch order, or XCD-banded (the first 8*P of the launch's blocks, P =
- * blocks/8, are dealt so that each of the 8 XCDs runs a contiguous band of
- * P tiles and shares its L2 between neighbours).  The choice is appended to
+ * launch order, or XCD-chunked (in every group of 64 consecutive tiles,
+ * each of the 8 XCDs runs 8 consecutive tiles, so that x-neighbours share
+ * its L2; tiles past the last whole group keep launch order).  The choice is appended to
  * a plain-text cache ($HV_TUNE_CACHE, else $HOME/.cache/hevi/tune.txt; one
  * line "key c_prep c_flux c_short", c = shape index 0..2 for 16x1, 8x2, 4x4,
- * plus 3 for the XCD-banded order; the last line of a key wins, and hv_tune
+ * plus 3 for the XCD-chunked order; the last line of a key wins, and hv_tune
  * rewrites the file with one line per key) that later
  * grids of the same kind read at creation.  tile_x_out (may be NULL)
  * receives the chosen x-extent of the three kinds, negated for the
- * XCD-banded order.  Synchronises the stream; does not change the state.
+ * XCD-chunked order.  Synchronises the stream; does not change the state.
  * (Addressing: the slow-flux kernel reaches the arrays of a launch group by
  * 32-bit byte offsets when every member's arrays are under 4 GiB, else by
  * 64-bit addresses; HV_ADDR64=1 in the environment at creation forces the

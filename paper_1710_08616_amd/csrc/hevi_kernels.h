@@ -86,7 +86,7 @@ struct Group {
     int ev;                 // short step: buffer of the explicit / old-time terms (src: forward-backward)
     int terrain;            // members of the group are terrain-following
     int damp;               // short step: damp the new values (members with damping data)
-    int xcd;                // 1: blocks in XCD-banded order (see block_order)
+    int xcd;                // 1: blocks in XCD-chunked order (see block_order)
     int off32;              // 1: every array of every member is under 4 GiB
 };
 

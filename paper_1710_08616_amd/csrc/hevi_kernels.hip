@@ -8,7 +8,7 @@
 // touches 4 (2) columns of contiguous memory.  Vertical neighbours live in the
 // adjacent lane of the same segment (DPP row shifts or shuffles); horizontal
 // neighbours are other columns and come through L1/L2.  A block covers a tile
-// of 16 columns (16x1, 8x2 or 4x4, in launch or XCD-banded order, as the
+// of 16 columns (16x1, 8x2 or 4x4, in launch or XCD-chunked order, as the
 // autotuner chose; the results do not depend on it).
 //
 // The per-column tridiagonal system of the vertically implicit part is solved
@@ -73,16 +73,24 @@ struct Where {
     bool active;
 };
 // Launch order of the blocks.  Workgroups go to the 8 XCDs (each with its own
-// L2) in turn, so in launch order neighbouring tiles land on different L2s.
-// The XCD-banded order hands XCD x the contiguous run x*P .. x*P + P-1 of the
-// first 8P blocks (P = nblocks / 8), so that most neighbour columns a tile
-// reads sit in the same L2; the autotuner decides whether it pays.
+// L2) in turn, so in launch order neighbouring tiles along x land on
+// different L2s.  The XCD-chunked order deals the tiles in runs of
+// kXcdChunk: within every group of 8 * kXcdChunk consecutive tiles, XCD x
+// gets the kXcdChunk consecutive tiles x * kXcdChunk ..; blocks past the last
+// whole group keep launch order.  Most x-neighbours then share an L2, while
+// all XCDs still stream through neighbouring memory at any moment (giving
+// each XCD one contiguous eighth of the domain instead was slower).  The
+// autotuner decides whether it pays.
+constexpr int kXcdChunk = 8;
 __device__ __forceinline__ int block_order(const Group &gr)
 {
     int b = (int)blockIdx.x;
     if (gr.xcd) {
-        const int per = gr.nblocks >> 3;
-        if (b < (per << 3)) b = (b & 7) * per + (b >> 3);
+        const int full = gr.nblocks / (8 * kXcdChunk) * (8 * kXcdChunk);
+        if (b < full) {
+            const int n = b >> 3;
+            b = (n / kXcdChunk) * (8 * kXcdChunk) + (b & 7) * kXcdChunk + n % kXcdChunk;
+        }
     }
     return b;
 }

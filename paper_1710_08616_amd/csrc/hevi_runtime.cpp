@@ -42,7 +42,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // tile shapes the autotuner tries: log2 of the columns along x (16x1, 8x2, 4x4);
 // a launch configuration is a shape and a block order (launch order or
-// XCD-banded): index c = shape + 3 * banded, c in 0..5
+// XCD-chunked): index c = shape + 3 * chunked, c in 0..5
 constexpr int kShapes[3] = {4, 3, 2};
 constexpr int kConfigs = 6;
 enum { KIND_PREP = 0, KIND_FLUX = 1, KIND_SHORT = 2, NKIND = 3 };

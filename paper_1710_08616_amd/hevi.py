@@ -252,7 +252,7 @@ class Domain:
     def tune(self):
         """Autotune the launch configurations; returns the chosen tile x-extent
         per kernel kind (slow prep, slow flux, short step), negative where the
-        XCD-banded block order won."""
+        XCD-chunked block order won."""
         out = (ctypes.c_int32 * 3)()
         self._check(load().hv_tune(self.handle, out))
         return list(out)

@@ -87,9 +87,10 @@ def test_tuned_tile_shapes_give_identical_results(hv, tmp_path, monkeypatch):
 
 def test_every_launch_configuration_is_bitwise(hv, tmp_path, monkeypatch):
     """Each of the six launch configurations (three tile shapes, launch order
-    or XCD-banded order), forced through the tune cache read at creation,
-    gives the untuned result bitwise.  90 16x1 tiles: the banded order deals
-    88 of them and leaves a tail of 2; two members make it the grouped form."""
+    or XCD-chunked order), forced through the tune cache read at creation,
+    gives the untuned result bitwise.  90 16x1 tiles (75 8x2, 80 4x4): the
+    chunked order deals 64 of them and leaves the rest in launch order; two
+    members make it the grouped form."""
     cache = tmp_path / "tune.txt"
     monkeypatch.setenv("HV_TUNE_CACHE", str(cache))
     ms = [inputs.make_state(40, 30, 32, seed=31, dt=8.0, n_short=3, noise=0.4, u_bg=6.0),

@@ -67,8 +67,12 @@
  * uniform flow staying bitwise steady; preservation of a uniform theta
  * field; discrete hydrostatic balance staying at rest; the Thomas solve
  * against a dense LU; the assembled tridiagonal against the brute-force
- * Jacobian of the vertical update equations; and the horizontal and vertical
- * acoustic modes against their closed-form amplification matrices.
+ * Jacobian of the vertical update equations; the horizontal and vertical
+ * acoustic modes against their closed-form amplification matrices; the
+ * gravity and acoustic modes of an isothermal atmosphere against their
+ * dispersion relation; closed forms of single stencil terms (a uniform
+ * specific velocity over a varying density, a potential temperature linear
+ * in height on stretched levels); and conservation of the total rho*theta.
  * or_energy() (a diagnostic): the closed-form energy of the isothermal rest
  * state, flat and over terrain, and the kinetic increment of a uniform flow.
  *

@@ -174,9 +174,10 @@ def step(s, dt=None, n_long=None, n_short=None, f32_storage=False, grav: float =
     return f
 
 
-def slow_sweep(s, fields=None, grav: float = GRAV) -> List[np.ndarray]:
-    """{S_U, S_V, S_W, R_Theta, theta_s, P0_s, C_s} of the given stage-input state."""
-    gh = _GridHolder(s, grav)
+def slow_sweep(s, fields=None, grav: float = GRAV, donor_cell: bool = False) -> List[np.ndarray]:
+    """{S_U, S_V, S_W, R_Theta, theta_s, P0_s, C_s} of the given stage-input state
+    (donor_cell: first-order upwind face values instead of Koren's, tests only)."""
+    gh = _GridHolder(s, grav, donor_cell=donor_cell)
     f = [_f64(x) for x in (s.fields if fields is None else fields)]
     c = (s.nz, s.ny, s.nx)
     out = [np.zeros(c), np.zeros(c), np.zeros((s.nz + 1, s.ny, s.nx)), np.zeros(c),

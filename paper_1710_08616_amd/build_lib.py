@@ -22,10 +22,6 @@ FLAGS = [
 ]
 
 
-PROBE_SRC = os.path.join(CSRC, "stream_probe.hip")
-PROBE = os.path.join(HERE, "stream_probe")
-
-
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     cmd = [HIPCC, *FLAGS, "-o", tmp, *SOURCES]
@@ -33,13 +29,6 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
-    # bandwidth probe used to state the achievable HBM ceiling
-    pflags = [f for f in FLAGS if f not in ("-shared", "-fPIC")]
-    cmd = [HIPCC, *pflags, "-o", PROBE + ".tmp", PROBE_SRC]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(PROBE + ".tmp", PROBE)
     return LIB
 
 

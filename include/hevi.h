@@ -180,7 +180,7 @@ int hv_trace_read(hv_grid_t g, int32_t kind, double *ms_total, int64_t *launches
 int hv_tune(hv_grid_t g, int32_t *tile_x_out);
 
 /* Lateral and upper damping, the relaxation kernel of the paper's Listing 1
- * (Sect. 3), applied after every short step.  The target of each prognostic
+ * (Sect. 2.1), applied after every short step.  The target of each prognostic
  * is the boundary state interpolated in time,
  *   X_target = mtratio (ref + bnd1) + tratio (ref + bnd2) - ref,
  * tratio = (t - t1)/(t2 - t1) clipped to [0, 1], mtratio = 1 - tratio, ref the

@@ -148,6 +148,23 @@ int hv_state_read(hv_grid_t g, int32_t field, double *host_out);
  * non-finite value anywhere propagates into it).  Synchronises the stream. */
 int hv_mass(hv_grid_t g, double *mass_out, double *energy_out);
 
+/* For callers that cannot allocate device memory or block (code between
+ * kernels of a tight serving loop, work a caller records into a HIP graph):
+ * the sums of hv_mass, enqueued on the grid's stream without any allocation
+ * or synchronisation.  Writes dev_out[0] = total mass and dev_out[1] =
+ * total energy of the current state (the same float64 values, in the same
+ * fixed order, that hv_mass returns); dev_out is caller-owned device memory
+ * of 2 doubles, written when the stream reaches the sums.  The partial sums
+ * live in a library-owned static device array of 1024 doubles per device
+ * (looked up at hv_grid_create, with the grid's device current); a grid whose
+ * sums need more partials is rejected with HV_ERR_ARG (none can: the
+ * partial count is capped at 1024).  The array is shared by every grid on a
+ * device and keeps the last call's partials: calls that overlap in time on
+ * one device (different streams or threads) race; calls on one stream are
+ * ordered.  HV_ERR_STATE before hv_state_init.  Does not check the mass for
+ * finiteness (read dev_out). */
+int hv_mass_noalloc(hv_grid_t g, double *dev_out);
+
 /* Kernel timing with HIP events on the grid's stream, a measurement aid.
  * hv_trace(g, 1) zeroes the totals and records an event pair around every
  * kernel launch that follows; hv_trace(g, 0) stops recording.

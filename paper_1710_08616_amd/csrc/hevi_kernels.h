@@ -88,6 +88,11 @@ struct Group {
     int damp;               // short step: damp the new values (members with damping data)
     int xcd;                // 1: blocks in XCD-chunked order (see block_order)
     int off32;              // 1: every array of every member is under 4 GiB
+    // sums only (single member): null, or partials in this array and the
+    // final sums written to out[slot] (the mass slot with out_add added)
+    double *part;
+    double *out;
+    double out_add;
 };
 
 // Blocks a member needs for a tile shape.
@@ -117,6 +122,13 @@ hipError_t launch_clock(const Group &gr, hipStream_t s);
 // gr.blk maps blocks to (member, partial).  Sums the perturbation mass
 // (energy = false) or the total energy of buffer gr.src into each member's sums.
 hipError_t launch_sums(int prec, int layout, int L, const Group &gr, bool energy, hipStream_t s);
+
+// Library-owned device scratch of the allocation-free sums: room for
+// kScratchDoubles float64 values (the partials of one grid) on every device
+// the library runs on.  *out receives its device address on the current
+// device, looked up once per device and kept.
+constexpr int kScratchDoubles = kMaxPartials;
+hipError_t scratch_address(double **out);
 
 // Seven-point diffusion step on one device array (nx*ny*nz values of type
 // prec 0 = double, 1 = float, in `layout`): out = q + kx lx + ky ly + kz lz.

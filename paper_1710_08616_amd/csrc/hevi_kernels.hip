@@ -39,6 +39,7 @@
 #include "hevi_kernels.h"
 
 #include <cstdint>
+#include <mutex>
 #include <type_traits>
 
 namespace hv {
@@ -1518,7 +1519,7 @@ __global__ __launch_bounds__(BLOCK) void k_sum_partial(Group gr)
         }
     }
     const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) m->partials[q] = s;
+    if (threadIdx.x == 0) (gr.part ? gr.part : m->partials)[q] = s;
 }
 
 // One block per member of the group: sum its partials in a fixed order
@@ -1527,16 +1528,24 @@ __global__ __launch_bounds__(BLOCK) void k_sum_final(Group gr, int slot)
 {
     __shared__ double sh[BLOCK];
     const MemberDev *m = gr.mem + (gr.nm == 1 ? gr.first : gr.ids[blockIdx.x]);
+    const double *part = gr.part ? gr.part : m->partials;
     double s = 0.0, c = 0.0;
     for (int q = threadIdx.x; q < m->npart; q += BLOCK) {
-        const double x = m->partials[q];
+        const double x = part[q];
         const double t = s + x;
         c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
         s = t;
     }
     const double tot = block_sum(s + c, sh);
-    if (threadIdx.x == 0) m->sums[slot] = tot;
+    if (threadIdx.x == 0) {
+        if (gr.out) gr.out[slot] = slot == 0 ? gr.out_add + tot : tot;
+        else m->sums[slot] = tot;
+    }
 }
+
+// Partials of the allocation-free sums (one grid at a time per device; see
+// scratch_address).
+static __device__ __align__(256) double scratch[kScratchDoubles];
 
 // --------------------------------------------------------------------------
 // seven-point diffusion (the bandwidth-model stencil): one read of each
@@ -1751,6 +1760,27 @@ hipError_t launch_short_step(int prec, int layout, int L, const Group &gr, doubl
 hipError_t launch_sums(int prec, int layout, int L, const Group &gr, bool energy, hipStream_t s)
 {
     return dispatch<RunSums>(prec, layout, L, gr, energy, s);
+}
+
+hipError_t scratch_address(double **out)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t r = hipGetDevice(&dev);
+    if (r != hipSuccess) return r;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        // the array's name is a host-side stand-in; the device address of
+        // this device's copy comes from the runtime
+        void *p = nullptr;
+        if ((r = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess) return r;
+        addr[dev] = (double *)p;
+    }
+    *out = addr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_clock(const Group &gr, hipStream_t s)

@@ -113,7 +113,9 @@ struct hv_ens {
     }
 };
 
-struct hv_grid : hv_ens {};
+struct hv_grid : hv_ens {
+    double *scratch = nullptr;   // this device's copy of the library scratch
+};
 
 namespace {
 
@@ -1104,6 +1106,10 @@ int hv_grid_create(const hv_grid_desc *desc, void *dev_workspace, size_t bytes, 
     if (!g) return fail(nullptr, HV_ERR_ARG, "out of host memory");
     const int rc = ens_create(g, 1, desc, dev_workspace, bytes, hip_stream);
     if (rc != HV_OK) { delete g; return rc; }
+    // set-up of the allocation-free sums: the device address of the library
+    // scratch on this device (looked up once per device)
+    const hipError_t r = hv::scratch_address(&g->scratch);
+    if (r != hipSuccess) { delete g; return hip_fail(nullptr, r, "scratch address"); }
     *out = g;
     return HV_OK;
 }
@@ -1132,6 +1138,29 @@ int hv_mass(hv_grid_t g, double *mass_out, double *energy_out)
 {
     if (!g) return fail(nullptr, HV_ERR_ARG, "handle is NULL");
     return member_mass(g, 0, mass_out, energy_out);
+}
+
+int hv_mass_noalloc(hv_grid_t g, double *dev_out)
+{
+    if (!g) return fail(nullptr, HV_ERR_ARG, "handle is NULL");
+    if (!dev_out) return fail(g, HV_ERR_ARG, "dev_out is NULL");
+    const MemberHost &m = g->m[0];
+    if (!m.have_state) return fail(g, HV_ERR_STATE, "mass before state_init");
+    if (m.dev.npart > hv::kScratchDoubles) {
+        char b[128];
+        std::snprintf(b, sizeof b, "grid needs %d partial sums, the scratch holds %d", m.dev.npart,
+                      hv::kScratchDoubles);
+        return fail(g, HV_ERR_ARG, b);
+    }
+    if (!g->scratch) return fail(g, HV_ERR_STATE, "no scratch address on this device");
+    hv::Group gm = group_launch(g, g->groups[0], -1, g->roles[0]);
+    gm.part = g->scratch;
+    gm.out = dev_out;
+    gm.out_add = m.mass_ref;
+    hipError_t r = hv::launch_sums(g->prec, g->layout, g->groups[0].L, gm, false, g->stream);
+    if (r == hipSuccess) r = hv::launch_sums(g->prec, g->layout, g->groups[0].L, gm, true, g->stream);
+    if (r != hipSuccess) return hip_fail(g, r, "allocation-free sums");
+    return HV_OK;
 }
 
 int hv_tune(hv_grid_t g, int32_t *tile_x_out)

@@ -30,7 +30,7 @@ EXPORTS = ("hv_workspace_bytes", "hv_grid_create", "hv_state_init", "hv_step", "
            "hv_mass", "hv_tune", "hv_trace", "hv_trace_read", "hv_grid_destroy", "hv_last_error",
            "hv_ens_workspace_bytes", "hv_ens_create", "hv_ens_state_init", "hv_ens_step",
            "hv_ens_state_read", "hv_ens_mass", "hv_ens_tune", "hv_ens_trace", "hv_ens_trace_read",
-           "hv_ens_destroy", "hv_ens_last_error", "hv_diffuse", "hv_damping", "hv_ens_damping")
+           "hv_ens_destroy", "hv_ens_last_error", "hv_diffuse", "hv_damping", "hv_ens_damping", "hv_mass_noalloc")
 K_SLOW_PREP, K_SLOW_FLUX, K_SHORT_STEP, K_MASS = 0, 1, 2, 3
 KERNEL_KINDS = {"slow_prep": K_SLOW_PREP, "slow_flux": K_SLOW_FLUX, "short_step": K_SHORT_STEP,
                 "mass": K_MASS}
@@ -81,6 +81,8 @@ def load():
     L.hv_state_read.argtypes = [ctypes.c_void_p, ctypes.c_int32, _dp]
     L.hv_mass.restype = ctypes.c_int
     L.hv_mass.argtypes = [ctypes.c_void_p, _dp, _dp]
+    L.hv_mass_noalloc.restype = ctypes.c_int
+    L.hv_mass_noalloc.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     L.hv_trace.restype = ctypes.c_int
     L.hv_trace.argtypes = [ctypes.c_void_p, ctypes.c_int32]
     L.hv_trace_read.restype = ctypes.c_int
@@ -248,6 +250,15 @@ class Domain:
         self._check(load().hv_mass(self.handle, ctypes.byref(m),
                                    ctypes.byref(e) if energy else None))
         return (m.value, e.value) if energy else m.value
+
+    def mass_noalloc(self, dev_out):
+        """hv_mass_noalloc: enqueue the mass and energy sums of the current state
+        into dev_out (a device float64 tensor of at least 2 values) on the grid's
+        stream; nothing is allocated and nothing waits."""
+        import torch
+        if dev_out.dtype != torch.float64 or dev_out.numel() < 2 or not dev_out.is_cuda:
+            raise ValueError("dev_out must be a device float64 tensor of >= 2 values")
+        return self._check(load().hv_mass_noalloc(self.handle, ctypes.c_void_p(dev_out.data_ptr())))
 
     def tune(self):
         """Autotune the launch configurations; returns the chosen tile x-extent

@@ -14,9 +14,9 @@ wind shear, mixed precision primary, error of each path against the float64
 GPU run), xl (2048x2048x64 over hills, for --layout kij / ijk), ensemble
 (48 members of uneven sizes), diffusion (the seven-point stencil of the
 paper's reduced weather application on 1024x1024x64, timed against its
-no-cache and perfect-cache bandwidth models).  --accuracy adds the per-field
-error of every path against the float64 oracle on the oracle-sized sub-run of
-the workload.
+no-cache and perfect-cache bandwidth models).  With the CPU baseline (the
+oracle timed on the host cores) comes the per-field error of every path
+against the oracle on the oracle-sized sub-run of the workload.
 
 Prints one JSON line.  Progress goes to stderr.
 """
@@ -152,14 +152,21 @@ def field_errors(got, ref):
     return out
 
 
-def accuracy_vs_oracle(hevi, sub, precs):
-    """Every path against the float64 oracle on an oracle-sized sub-run of the
-    workload (same generator), after its full number of long steps."""
-    from oracle import oracle
-    log(f"[bench] accuracy: oracle {sub.nx}x{sub.ny}x{sub.nz}, {sub.n_long} long steps")
-    t0 = time.perf_counter()
-    ref = oracle.step(sub)
-    log(f"[bench] accuracy: oracle took {time.perf_counter() - t0:.1f} s")
+def twin_tolerances(case: str):
+    """The frozen per-field bars of the reduced-precision paths for a sub-run
+    (10x the binary32-storage twin of the oracle), or None."""
+    path = os.path.join(ROOT, "tests", "golden", "twin_tolerances.json")
+    try:
+        return json.load(open(path))["cases"][case]["tolerance"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def accuracy_vs_oracle(hevi, sub, ref, precs, case):
+    """Every path against the float64 oracle's result `ref` on an oracle-sized
+    sub-run of the workload (same generator), after its full number of long
+    steps; reduced-precision paths against their frozen per-field bars."""
+    tol = twin_tolerances(case)
     out = {}
     for p in precs:
         d = hevi.Domain(sub, precision=p)
@@ -168,9 +175,18 @@ def accuracy_vs_oracle(hevi, sub, precs):
         got = d.read_all()
         m1 = d.mass()
         d.close()
-        out[p] = {"fields": field_errors(got, ref), "mass_drift_rel": abs(m1 - m0) / m0}
+        fe = field_errors(got, ref)
+        rec = {"fields": fe, "mass_drift_rel": abs(m1 - m0) / m0}
+        if p != "fp64" and tol is not None:
+            rec["within_tolerance"] = all(fe[f]["max_rel"] <= tol[f]["max_rel"] and
+                                          fe[f]["rms_rel"] <= tol[f]["rms_rel"] for f in fe)
+        elif p == "fp64":
+            rec["within_tolerance"] = all(fe[f]["max_rel"] <= 1e-11 for f in fe)
+        out[p] = rec
+        log(f"[bench] accuracy {p}: worst max {max(v['max_rel'] for v in fe.values()):.2e} of "
+            f"the range, within tolerance: {rec.get('within_tolerance')}")
     return {"sub_run": f"{sub.nx}x{sub.ny}x{sub.nz}, {sub.n_long} long steps, n={sub.n_short}",
-            "per_precision": out}
+            "tolerance": tol, "per_precision": out}
 
 
 def time_ensemble(hevi, members, prec, steps, warmup, layout="kij", tune=True):
@@ -266,28 +282,50 @@ def time_diffusion(hevi, prec, steps, warmup, layout="kij", n=1024, nz=64):
             "speedup_vs_no_cache_model": t_nocache / ms}
 
 
-def cpu_baseline(steps: int = 4, n: int = 512, terrain: bool = False):
-    """The FP64 oracle on a bounded sample of the same workload: an n x n x 64
-    domain from the same generator (16 bubbles; over hills with shear for the
-    terrain workload), `steps` long steps."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(s, sub):
+    """The FP64 oracle on the host cores, as a baseline: one long step of the
+    workload at its full shape on all cores, one long step of the
+    oracle-sized sub-run on one thread, and the whole sub-run on all cores
+    (cell-updates/s each).  Also returns the sub-run's final fields, the
+    reference of the accuracy check."""
     from oracle import oracle
-    from paper_1710_08616_amd import inputs
-    seed = 1712 if terrain else 1711
-    bub = inputs.random_bubbles(seed, 16, n * 2000.0, n * 2000.0)
-    if terrain:
-        h = inputs.orography(n, n, 2000.0, 2000.0, seed)
-        s = inputs.make_state(n, n, 64, seed=seed, bubbles=bub, u_bg=0.0, shear=30.0, terrain=h,
-                              dt=10.0, n_short=6)
-    else:
-        s = inputs.make_state(n, n, 64, seed=seed, bubbles=bub, dt=10.0, n_short=6)
     oracle.lib()
+    cores = oracle.threads()
     t0 = time.perf_counter()
-    oracle.step(s, n_long=steps)
+    oracle.step(s, n_long=1)
     sec = time.perf_counter() - t0
-    return {"value": s.cells * steps / sec, "unit": "cell-updates/s", "cores": oracle.threads(),
-            "kind": "oracle",
-            "sample": f"{n}x{n}x64 domain of the same generator{' over hills' if terrain else ''}, "
-                      f"{steps} long steps (n=6), {sec:.1f} s"}
+    oracle.set_threads(1)
+    try:
+        t1 = time.perf_counter()
+        oracle.step(sub, n_long=1)
+        sec1 = time.perf_counter() - t1
+    finally:
+        oracle.set_threads(cores)
+    log(f"[bench] oracle: {sub.nx}x{sub.ny}x{sub.nz}, {sub.n_long} long steps")
+    t2 = time.perf_counter()
+    ref = oracle.step(sub)
+    sec2 = time.perf_counter() - t2
+    rec = {"value": s.cells / sec, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+           "sample": f"one long step (n={s.n_short}) of the {s.nx}x{s.ny}x{s.nz} workload itself, "
+                     f"{sec:.1f} s on {cores} threads",
+           "single_thread": {"value": sub.cells / sec1, "unit": "cell-updates/s", "cores": 1,
+                             "sample": f"one long step of the {sub.nx}x{sub.ny}x{sub.nz} sub-run, "
+                                       f"{sec1:.2f} s"},
+           "sub_run": {"value": sub.cells * sub.n_long / sec2, "unit": "cell-updates/s",
+                       "cores": cores, "sample": f"{sub.n_long} long steps of the sub-run, "
+                                                 f"{sec2:.1f} s"},
+           "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+    return rec, ref
 
 
 def main():
@@ -309,9 +347,10 @@ def main():
                     help="skip the autotuner: keep the launch configurations of the tune "
                          "cache ($HV_TUNE_CACHE) or the defaults (the counter runs use this so "
                          "that their passes measure one configuration)")
-    ap.add_argument("--accuracy", action="store_true",
-                    help="per-field error of every path against the float64 oracle on the "
-                         "oracle-sized sub-run")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the per-field error of every path against the float64 oracle "
+                         "on the oracle-sized sub-run (run by default with the CPU baseline, "
+                         "whose sub-run it compares with)")
     args = ap.parse_args()
     if args.precisions is None:
         args.precisions = {"terrain": "mixed,fp64", "xl": "fp32,mixed", "ensemble": "fp32,mixed",
@@ -425,15 +464,17 @@ def main():
     if rec:
         # the counters were taken with this tile x-extent (negative: XCD-chunked)
         roofline["traffic_tile_x"] = rec.get("tile_x")
+    case = {"large": "large_sub", "terrain": "terrain_sub"}.get(args.workload, "small")
+    sub = inputs.workload(case)
     cpu = None
+    accuracy = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle baseline")
-        cpu = cpu_baseline(terrain=terrain)
-        log(f"[bench] oracle: {cpu['value']:.3e} cell-updates/s on {cpu['cores']} threads")
-    accuracy = None
-    if args.accuracy:
-        sub = {"large": "large_sub", "terrain": "terrain_sub"}.get(args.workload, "small")
-        accuracy = accuracy_vs_oracle(hevi, inputs.workload(sub), precs)
+        cpu, sub_ref = cpu_baseline(s, sub)
+        log(f"[bench] oracle: {cpu['value']:.3e} cell-updates/s on {cpu['cores']} threads, "
+            f"{cpu['single_thread']['value']:.3e} on one")
+        if not args.no_accuracy and args.short == "fb" and not args.damping:
+            accuracy = accuracy_vs_oracle(hevi, sub, sub_ref, precs, case)
     out = {
         "metric": METRIC,
         "value": r["cell_updates_per_s"],

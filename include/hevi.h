@@ -61,7 +61,8 @@ enum {
     HV_ERR_HIP = -2,          /* a HIP runtime call failed (see hv_last_error)*/
     HV_ERR_STATE = -3,        /* step/read/mass before hv_state_init          */
     HV_ERR_NONFINITE = -4,    /* the FP64 mass sum is not finite              */
-    HV_ERR_UNSUPPORTED = -5   /* valid request the library does not implement */
+    HV_ERR_UNSUPPORTED = -5,  /* valid request the library does not implement */
+    HV_ERR_DRIFT = -6         /* the total mass left the grid's drift bound    */
 };
 
 /* Arithmetic of the stencil sweeps / of the column solve and global sums:
@@ -102,6 +103,16 @@ typedef struct {
     double div_damp;           /* must be 0                                  */
     int32_t short_scheme;      /* HV_SHORT_FB or HV_SHORT_RK2                */
     int32_t damping;           /* 1: reserve workspace for hv_damping        */
+    double mass_drift_bound;   /* failure detection: after every long step the
+                                  device compares the total mass M with M0 of
+                                  hv_state_init; |M - M0| / M0 above this bound
+                                  (or a non-finite M) sets a sticky flag that
+                                  hv_mass and hv_state_read report as
+                                  HV_ERR_DRIFT.  0: the default, 1e-9 (far
+                                  above the rounding drift of any precision),
+                                  or no check when damping = 1 (relaxation
+                                  toward boundary data does not conserve
+                                  mass); < 0: no check                        */
 } hv_grid_desc;
 
 /* Bytes of device workspace the grid needs; 0 if the description is invalid
@@ -138,14 +149,19 @@ int hv_step(hv_grid_t g, double dt, int32_t n_long, int32_t n_short);
 
 /* Copy one field back to the host in canonical float64 layout (the paper's
  * copy-out at output time).  host_out holds nx*ny*nz values, or
- * nx*ny*(nz+1) for HV_RHOW.  Synchronises the stream. */
+ * nx*ny*(nz+1) for HV_RHOW.  Synchronises the stream.  The values are
+ * written in every case; the call then returns HV_ERR_NONFINITE if any of
+ * them is not finite, else HV_ERR_DRIFT if the mass drift bound was crossed
+ * since hv_state_init. */
 int hv_state_read(hv_grid_t g, int32_t field, double *host_out);
 
 /* Total mass sum (rho_ref + rho') J dx dy dzeta and the diagnostic total energy
  * (kinetic + internal + potential) of the current state, in float64 with a
  * fixed summation order.  Either output pointer may be NULL.  Returns
  * HV_ERR_NONFINITE if the mass of the current state is not finite (a
- * non-finite value anywhere propagates into it).  Synchronises the stream. */
+ * non-finite value anywhere propagates into it), else HV_ERR_DRIFT if the
+ * mass drift bound was crossed after some long step since hv_state_init
+ * (the outputs are written in both cases).  Synchronises the stream. */
 int hv_mass(hv_grid_t g, double *mass_out, double *energy_out);
 
 /* For callers that cannot allocate device memory or block (code between

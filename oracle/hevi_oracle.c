@@ -1093,6 +1093,16 @@ int or_threads(void)
 #endif
 }
 
+/* Set that number (n >= 1); results do not depend on it. */
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------
  * Seven-point diffusion, the stencil that dominates the paper's reduced
  * weather application (Sect. 4, performance model of no-cache and

@@ -81,6 +81,8 @@ def lib():
         L.or_damp.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double]
         L.or_threads.restype = ctypes.c_int
         L.or_threads.argtypes = []
+        L.or_set_threads.restype = None
+        L.or_set_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -202,6 +204,11 @@ def short_step(s, slow, dtau, fields=None, grav: float = GRAV) -> List[np.ndarra
 def threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(lib().or_threads())
+
+
+def set_threads(n: int) -> None:
+    """Number of OpenMP threads for the following calls (bitwise the same results)."""
+    lib().or_set_threads(int(n))
 
 
 def koren_phi(dm: float, dp: float) -> float:

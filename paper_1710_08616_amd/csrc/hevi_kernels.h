@@ -57,7 +57,12 @@ struct MemberDev {
     double rdx, rdy, beta, dt;   // dt: long step of this member
     const double *vm;
     double *partials;
-    double *sums;                // [0] perturbation mass, [1] energy, [2] model time
+    double *sums;                // [0] perturbation mass, [1] energy, [2] model time,
+                                 // [3] perturbation mass at state_init, [4] drift
+                                 // flag (1 once the bound was crossed), [5] largest
+                                 // relative drift seen
+    double mass_ref;             // reference mass (rho_ref J dx dy dzeta summed)
+    double drift_bound;          // relative mass drift bound, <= 0: no check
     void *st[4][5];              // rho', U, V, W, Theta' of the state buffers
                                  // ([3]: first-stage value of the Runge-Kutta short step)
     void *slow[7];               // S_U, S_V, S_W, R_Theta, theta_s, P0_s, C_s
@@ -93,7 +98,10 @@ struct Group {
     double *part;
     double *out;
     double out_add;
+    int mass_init;          // sums: member id + 1 whose mass is recorded as its
+                            // state_init value (0: none)
 };
+constexpr int kSums = 8;    // doubles of a member's sums array
 
 // Blocks a member needs for a tile shape.
 inline int tiles_of(int nx, int ny, int ti_log2)

@@ -1527,7 +1527,8 @@ __global__ __launch_bounds__(BLOCK) void k_sum_partial(Group gr)
 __global__ __launch_bounds__(BLOCK) void k_sum_final(Group gr, int slot)
 {
     __shared__ double sh[BLOCK];
-    const MemberDev *m = gr.mem + (gr.nm == 1 ? gr.first : gr.ids[blockIdx.x]);
+    const int id = gr.nm == 1 ? gr.first : gr.ids[blockIdx.x];
+    const MemberDev *m = gr.mem + id;
     const double *part = gr.part ? gr.part : m->partials;
     double s = 0.0, c = 0.0;
     for (int q = threadIdx.x; q < m->npart; q += BLOCK) {
@@ -1538,8 +1539,23 @@ __global__ __launch_bounds__(BLOCK) void k_sum_final(Group gr, int slot)
     }
     const double tot = block_sum(s + c, sh);
     if (threadIdx.x == 0) {
-        if (gr.out) gr.out[slot] = slot == 0 ? gr.out_add + tot : tot;
-        else m->sums[slot] = tot;
+        if (gr.out) {
+            gr.out[slot] = slot == 0 ? gr.out_add + tot : tot;
+        } else {
+            double *sm = m->sums;
+            sm[slot] = tot;
+            if (slot == 0 && gr.mass_init == id + 1) {
+                sm[3] = tot;
+                sm[4] = 0.0;
+                sm[5] = 0.0;
+            } else if (slot == 0 && m->drift_bound > 0.0) {
+                // failure detection: relative drift of the total mass since
+                // state_init (a non-finite mass fails both comparisons)
+                const double d = fabs(tot - sm[3]) / (m->mass_ref + sm[3]);
+                if (!(d <= sm[5])) sm[5] = d;
+                if (!(d <= m->drift_bound)) sm[4] = 1.0;
+            }
+        }
     }
 }
 

@@ -38,6 +38,7 @@ namespace {
 
 thread_local std::string g_global_error = "no error";
 constexpr size_t kAlign = 256;
+constexpr double kDefaultDriftBound = 1e-9;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // tile shapes the autotuner tries: log2 of the columns along x (16x1, 8x2, 4x4);
@@ -149,6 +150,7 @@ std::string check_desc(const hv_grid_desc *d)
     if (!(d->beta >= 0.5 && d->beta <= 1.0)) return "beta must be in [0.5, 1]";
     if (d->short_scheme != HV_SHORT_FB && d->short_scheme != HV_SHORT_RK2) return "unknown short_scheme";
     if (d->damping != 0 && d->damping != 1) return "damping must be 0 or 1";
+    if (std::isnan(d->mass_drift_bound)) return "mass_drift_bound must not be NaN";
     if (d->terrain) {
         const double H = d->zeta_faces[d->nz];
         const size_t nxy = (size_t)d->nx * d->ny;
@@ -235,7 +237,7 @@ Plan make_plan(int n, const hv_grid_desc *d)
         }
         c.take(hv::vm_bytes(d[q].nz));
         c.take(sizeof(double) * (size_t)hv::partials_of(d[q].nx, d[q].ny));
-        c.take(sizeof(double) * 4);
+        c.take(sizeof(double) * hv::kSums);
         p.member_off.push_back(start);
     }
     p.total = c.off;
@@ -669,7 +671,10 @@ int ens_create(hv_ens *e, int n, const hv_grid_desc *descs, void *ws, size_t byt
         }
         v.vm = (const double *)(base + c.take(hv::vm_bytes(m.nz)));
         v.partials = (double *)(base + c.take(sizeof(double) * (size_t)v.npart));
-        v.sums = (double *)(base + c.take(sizeof(double) * 4));
+        v.sums = (double *)(base + c.take(sizeof(double) * hv::kSums));
+        v.mass_ref = 0.0;
+        v.drift_bound = d.mass_drift_bound > 0.0 ? d.mass_drift_bound
+                        : (d.mass_drift_bound == 0.0 && !d.damping ? kDefaultDriftBound : 0.0);
     }
     auto gm = group_members(n, descs);
     e->groups.resize(gm.size());
@@ -727,6 +732,13 @@ int ens_create(hv_ens *e, int n, const hv_grid_desc *descs, void *ws, size_t byt
         (r = hipEventCreateWithFlags(&e->join, hipEventDisableTiming)) != hipSuccess)
         return hip_fail(nullptr, r, "hipEventCreate");
     return HV_OK;
+}
+
+hipError_t upload_table(hv_ens *e)
+{
+    std::vector<hv::MemberDev> table(e->n);
+    for (int q = 0; q < e->n; ++q) table[q] = e->m[q].dev;
+    return hipMemcpy(e->d_mem, table.data(), sizeof(hv::MemberDev) * e->n, hipMemcpyHostToDevice);
 }
 
 int member_init(hv_ens *e, int q, const double *const fields[5], const double *rho_ref,
@@ -805,12 +817,16 @@ int member_init(hv_ens *e, int q, const double *const fields[5], const double *r
             add(rho_ref[(size_t)k * nxy + col] * vol * (1.0 - m.h[col] / H));
     }
     m.mass_ref = s + c;
+    m.dev.mass_ref = m.mass_ref;
+    if ((r = upload_table(e)) != hipSuccess) return hip_fail(e, r, "upload member table");
     const double zero = 0.0;   // model time
     if ((r = hipMemcpy(m.dev.sums + 2, &zero, sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, r, "hipMemcpy(time)");
     m.have_state = true;
     for (auto &g : e->groups) {
-        const hv::Group gm = group_launch(e, g, -1, e->roles[0]);
+        // the mass of this state is the reference of member q's drift check
+        hv::Group gm = group_launch(e, g, -1, e->roles[0]);
+        gm.mass_init = q + 1;
         r = hv::launch_sums(e->prec, e->layout, g.L, gm, false, e->stream);
         if (r != hipSuccess) return hip_fail(e, r, "mass after state_init");
     }
@@ -884,6 +900,22 @@ int ens_step(hv_ens *e, const double *dts, int n_long, int n_short)
     return HV_OK;
 }
 
+// HV_ERR_DRIFT once a long step left the member's mass drift bound (the
+// device's sticky flag); call with the stream synchronised.
+int check_drift(hv_ens *e, const MemberHost &m)
+{
+    if (!(m.dev.drift_bound > 0.0)) return HV_OK;
+    double h[2] = {0.0, 0.0};
+    hipError_t r = hipMemcpy(h, m.dev.sums + 4, 2 * sizeof(double), hipMemcpyDeviceToHost);
+    if (r != hipSuccess) return hip_fail(e, r, "read drift flag");
+    if (h[0] != 0.0) {
+        char b[160];
+        std::snprintf(b, sizeof b, "mass drift %.3e exceeds the bound %.3e", h[1], m.dev.drift_bound);
+        return fail(e, HV_ERR_DRIFT, b);
+    }
+    return HV_OK;
+}
+
 int member_read(hv_ens *e, int q, int field, double *out)
 {
     if (q < 0 || q >= e->n) return fail(e, HV_ERR_ARG, "member index out of range");
@@ -909,7 +941,18 @@ int member_read(hv_ens *e, int q, int field, double *out)
         const size_t nxy = (size_t)m.nx * m.ny;
         for (size_t c = 0; c < nxy; ++c) out[nxy * m.nz + c] = 0.0;
     }
-    return HV_OK;
+    // failure detection: non-finite values, then the device's drift flag
+    const size_t nxy = (size_t)m.nx * m.ny;
+    const int levels = field == HV_RHOW ? m.nz + 1 : m.nz;
+    std::vector<char> bad(levels, 0);
+    parallel_rows(levels, nxy, [&](int k0, int k1) {
+        for (int k = k0; k < k1; ++k)
+            for (size_t c = 0; c < nxy; ++c)
+                if (!std::isfinite(out[(size_t)k * nxy + c])) { bad[k] = 1; break; }
+    });
+    for (char b : bad)
+        if (b) return fail(e, HV_ERR_NONFINITE, "the field holds non-finite values");
+    return check_drift(e, m);
 }
 
 int member_mass(hv_ens *e, int q, double *mass, double *energy)
@@ -932,15 +975,9 @@ int member_mass(hv_ens *e, int q, double *mass, double *energy)
     if (mass) *mass = ms;
     if (energy) *energy = h[1];
     if (!std::isfinite(ms)) return fail(e, HV_ERR_NONFINITE, "mass sum is not finite");
-    return HV_OK;
+    return check_drift(e, m);
 }
 
-hipError_t upload_table(hv_ens *e)
-{
-    std::vector<hv::MemberDev> table(e->n);
-    for (int q = 0; q < e->n; ++q) table[q] = e->m[q].dev;
-    return hipMemcpy(e->d_mem, table.data(), sizeof(hv::MemberDev) * e->n, hipMemcpyHostToDevice);
-}
 
 int member_damping(hv_ens *e, int q, const double *nu_lat, const double *nu_top,
                    const double *const bnd1[5], const double *const bnd2[5], double t1, double t2,

@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhevi.so")
 
 HV_OK, HV_ERR_ARG, HV_ERR_HIP, HV_ERR_STATE, HV_ERR_NONFINITE, HV_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+HV_ERR_DRIFT = -6
 FP64, FP32, MIXED = 0, 1, 2
 IJK, KIJ = 0, 1
 RHO_PTB, RHOU, RHOV, RHOW, RHOTHETA_PTB = 0, 1, 2, 3, 4
@@ -50,7 +51,8 @@ class GridDesc(ctypes.Structure):
                 ("zeta_faces", _dp), ("terrain", _dp),
                 ("precision", ctypes.c_int32), ("layout", ctypes.c_int32),
                 ("beta", ctypes.c_double), ("div_damp", ctypes.c_double),
-                ("short_scheme", ctypes.c_int32), ("damping", ctypes.c_int32)]
+                ("short_scheme", ctypes.c_int32), ("damping", ctypes.c_int32),
+                ("mass_drift_bound", ctypes.c_double)]
 
 
 _lib = None
@@ -135,11 +137,12 @@ def load():
 
 
 def make_desc(nx, ny, nz, dx, dy, zf, precision="fp32", layout="kij", beta=0.55, terrain=None,
-              short="fb", damping=False):
+              short="fb", damping=False, drift_bound=0.0):
     """A filled hv_grid_desc plus the arrays it points into (keep them alive
     until the grid is created).  terrain: (ny, nx) surface heights or None;
     short: "fb" (forward-backward) or "rk2" (two-stage Runge-Kutta) short step;
-    damping: reserve workspace for lateral / upper damping data."""
+    damping: reserve workspace for lateral / upper damping data; drift_bound: the
+    relative mass drift bound of the failure check (0: library default, < 0: off)."""
     zf = np.ascontiguousarray(zf, dtype=np.float64)
     keep = [zf]
     tp = None
@@ -154,7 +157,7 @@ def make_desc(nx, ny, nz, dx, dy, zf, precision="fp32", layout="kij", beta=0.55,
                  PRECISIONS[precision] if isinstance(precision, str) else int(precision),
                  LAYOUTS[layout] if isinstance(layout, str) else int(layout),
                  float(beta), 0.0, SHORT_SCHEMES[short] if isinstance(short, str) else int(short),
-                 1 if damping else 0)
+                 1 if damping else 0, float(drift_bound))
     return d, keep
 
 
@@ -189,7 +192,7 @@ class Domain:
     """
 
     def __init__(self, state, precision="fp32", layout="kij", device="cuda", stream=None,
-                 init=True, short="fb"):
+                 init=True, short="fb", drift_bound=0.0):
         import torch
         self._torch = torch
         L = load()
@@ -197,7 +200,8 @@ class Domain:
         dmp = getattr(state, "damping", None)
         self.desc, self._keep = make_desc(state.nx, state.ny, state.nz, state.dx, state.dy,
                                           state.zf, precision, layout, getattr(state, "beta", 0.55),
-                                          getattr(state, "terrain", None), short, dmp is not None)
+                                          getattr(state, "terrain", None), short, dmp is not None,
+                                          drift_bound)
         nbytes = workspace_bytes(self.desc)
         if nbytes == 0:
             raise HvError(HV_ERR_ARG, last_error())

@@ -167,10 +167,15 @@ class State:
     def copy(self) -> "State":
         return dataclasses.replace(self, fields=[f.copy() for f in self.fields])
 
-    def as_f32(self) -> "State":
-        """The same state with every field rounded to binary32 (kept as float64)."""
-        return dataclasses.replace(
-            self, fields=[f.astype(np.float32).astype(np.float64) for f in self.fields])
+    def as_f32(self, reference: bool = False) -> "State":
+        """The same state with every field rounded to binary32 (kept as float64);
+        with reference=True the reference arrays are rounded as well (what a
+        binary32 path holds of them)."""
+        r32 = lambda a: np.asarray(a, dtype=np.float64).astype(np.float32).astype(np.float64)
+        out = dataclasses.replace(self, fields=[r32(f) for f in self.fields])
+        if reference:
+            out.rho_ref, out.rt_ref, out.p_ref = r32(self.rho_ref), r32(self.rt_ref), r32(self.p_ref)
+        return out
 
 
 def true_heights(zc: np.ndarray, terrain: Optional[np.ndarray]) -> np.ndarray:

@@ -55,6 +55,7 @@ def test_workspace_bytes_scales_with_precision(hv):
     (dict(nx=2), "nx and ny"), (dict(nz=40, zf=np.linspace(0, 1e4, 41)), "nz must be"),
     (dict(dx=0.0), "dx and dy"), (dict(beta=0.4), "beta"), (dict(precision=7), "precision"),
     (dict(layout=5), "layout"), (dict(zf=-np.linspace(0, 1e4, 33)), "zeta_faces"),
+    (dict(drift_bound=float("nan")), "mass_drift_bound"),
 ])
 def test_invalid_descriptions_are_rejected(hv, kw, needle):
     d, _z = _desc(hv, **kw)

@@ -74,7 +74,7 @@ def test_reduced_precision_damped_step_within_twin(hv, oracle, prec):
     s = _state(False, nz=64, seed=9)
     print(f"case: damping {prec}", flush=True)
     ref = oracle.step(s, n_long=3)
-    twin = oracle.step(s.as_f32(), n_long=3, f32_storage=True)
+    twin = oracle.step(s.as_f32(reference=True), n_long=3, f32_storage=True)
     got = _gpu(hv, s, prec, 3)
     for name, a, b, t in zip(inputs.FIELD_NAMES, got, ref, twin):
         tol = 10.0 * _rel(t, b)

@@ -80,7 +80,7 @@ def _check(hv, oracle, s, prec):
         print(f"case: full {s.name} {prec}: sample ({ic}, {jc})", flush=True)
         p = _patch(s, ic, jc)
         ref = oracle.step(p, n_long=1)
-        twin = oracle.step(p.as_f32(), n_long=1, f32_storage=True) if prec != "fp64" else None
+        twin = oracle.step(p.as_f32(reference=True), n_long=1, f32_storage=True) if prec != "fp64" else None
         c = PATCH // 2
         for f, name in enumerate(inputs.FIELD_NAMES):
             a = _core(got[f], ic, jc, s.nx, s.ny)

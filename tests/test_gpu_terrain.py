@@ -64,7 +64,7 @@ def test_terrain_reduced_precision_within_twin_tolerance(hv, oracle, prec):
     s = _hill_state(40, 32, 32, seed=5)
     print(f"case: terrain 40x32x32 {prec}", flush=True)
     ref = oracle.step(s)
-    twin = oracle.step(s.as_f32(), f32_storage=True)
+    twin = oracle.step(s.as_f32(reference=True), f32_storage=True)
     got, _ = _run(hv, s, prec)
     for name, a, b, t in zip(inputs.FIELD_NAMES, got, ref, twin):
         tol = 10.0 * _rel(t, b)

@@ -1,0 +1,94 @@
+"""The full 48-member ensemble (229M cells, nx, ny in 128..512, nz in 32/64,
+per-member dt) on sampled members: after 2 long steps of the whole ensemble,
+in the tuned launch configurations,
+
+- the smallest, the largest and one member of the other nz run alone give
+  bitwise the ensemble's values (float32 and mixed);
+- the smallest member matches the oracle: mixed within 10x the oracle's
+  binary32-storage twin per field, float64 (its own ensemble) within 1e-11
+  of the range;
+- every member's mass drifts by at most 1e-11 of itself.
+"""
+import numpy as np
+import pytest
+
+from paper_1710_08616_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+N_LONG = 2
+
+
+@pytest.fixture(scope="module")
+def hv():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1710_08616_amd import hevi
+    hevi.load()
+    return hevi
+
+
+@pytest.fixture(scope="module")
+def members():
+    return inputs.ensemble()
+
+
+def _rel(a, b):
+    r = np.ptp(b)
+    return np.abs(a - b).max() / (r if r > 0 else 1.0)
+
+
+def _sample(ms):
+    cells = [m.cells for m in ms]
+    lo, hi = int(np.argmin(cells)), int(np.argmax(cells))
+    other = next(q for q, m in enumerate(ms) if m.nz != ms[lo].nz)
+    return sorted({lo, hi, other}), lo
+
+
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+def test_sampled_members_of_the_full_ensemble(hv, oracle, members, prec):
+    import torch
+    picks, lo = _sample(members)
+    print(f"case: 48-member ensemble {prec}, sampled members {picks}", flush=True)
+    e = hv.Ensemble(members, precision=prec)
+    e.tune()
+    m0 = [e.mass(q) for q in range(e.n)]
+    e.step(N_LONG, members[0].n_short)
+    for q in range(e.n):
+        m1 = e.mass(q)
+        assert abs(m1 - m0[q]) <= 1e-11 * m0[q], (q, m0[q], m1)
+    got = {q: e.read_all(q) for q in picks}
+    e.close()
+    del e
+    torch.cuda.empty_cache()
+    for q in picks:
+        s = members[q]
+        print(f"  member {q}: {s.nx}x{s.ny}x{s.nz} alone", flush=True)
+        d = hv.Domain(s, precision=prec)
+        d.step(s.dt, N_LONG, s.n_short)
+        alone = d.read_all()
+        d.close()
+        for a, b in zip(got[q], alone):
+            assert np.array_equal(a, b), q
+    if prec == "mixed":
+        s = members[lo]
+        ref = oracle.step(s, n_long=N_LONG)
+        twin = oracle.step(s.as_f32(reference=True), n_long=N_LONG, f32_storage=True)
+        for name, a, b, t in zip(inputs.FIELD_NAMES, got[lo], ref, twin):
+            tol = 10.0 * _rel(t, b)
+            assert _rel(a, b) <= tol, (lo, name, _rel(a, b), tol)
+
+
+def test_smallest_member_fp64_matches_oracle(hv, oracle, members):
+    import torch
+    _, lo = _sample(members)
+    print(f"case: 48-member ensemble fp64, member {lo} vs oracle", flush=True)
+    e = hv.Ensemble(members, precision="fp64")
+    e.step(N_LONG, members[0].n_short)
+    got = e.read_all(lo)
+    e.close()
+    del e
+    torch.cuda.empty_cache()
+    ref = oracle.step(members[lo], n_long=N_LONG)
+    for name, a, b in zip(inputs.FIELD_NAMES, got, ref):
+        assert _rel(a, b) <= 1e-11, (name, _rel(a, b))

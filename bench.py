@@ -56,14 +56,16 @@ def short_step_bytes(b: int, cells: int) -> int:
 
 
 def kernel_digest() -> str:
-    """Digest of the kernel source with comments and blank lines removed, so
-    that a comment edit does not invalidate the recorded counters."""
-    src = os.path.join(ROOT, "paper_1710_08616_amd", "csrc", "hevi_kernels.hip")
+    """Digest of the sources the column-fastest kernels are built from, with
+    comments and blank lines removed, so that a comment edit does not
+    invalidate the recorded counters."""
     code = []
-    for line in open(src, encoding="utf-8"):
-        line = line.split("//", 1)[0].rstrip()
-        if line:
-            code.append(line)
+    for name in ("hevi_kernels.hip", "hevi_device.h"):
+        src = os.path.join(ROOT, "paper_1710_08616_amd", "csrc", name)
+        for line in open(src, encoding="utf-8"):
+            line = line.split("//", 1)[0].rstrip()
+            if line:
+                code.append(line)
     return hashlib.sha256("\n".join(code).encode()).hexdigest()[:16]
 
 
@@ -94,8 +96,10 @@ def time_precision(hevi, s, prec, steps, warmup, layout="kij", keep=False, short
         # the autotuner times each launch configuration per kernel kind on this state
         # (results are bitwise independent of the shape; the state is left
         # unchanged)
-        tiles = d.tune()
-        log(f"[bench] {prec}: tiles (x-extent per kind) {tiles}")
+        tiles, lanes = d.tune()
+        tiles = {"tile_x": tiles, "lanes_per_column": lanes}
+        log(f"[bench] {prec}: tiles (x-extent per kind) {tiles['tile_x']}, lanes per column "
+            f"{lanes}")
     if warmup:
         d.step(s.dt, warmup, s.n_short)
     m0 = d.mass()
@@ -133,7 +137,7 @@ def time_precision(hevi, s, prec, steps, warmup, layout="kij", keep=False, short
         "kernels_ms_avg": {k: (v[0] / v[1] if v[1] else None) for k, v in kern.items()},
         "kernels_launches": {k: v[1] for k, v in kern.items()},
         "kernels_ms_total": {k: v[0] for k, v in kern.items()},
-        "tile_x": tiles,
+        "launch_config": tiles,
     }
     log(f"[bench] {prec}: {res['ms_per_step']:.3f} ms/step (graph replay {res['graph_ms_per_step']:.3f}), "
         f"{res['cell_updates_per_s']:.3e} cell-updates/s, model {res['model_gbps']:.0f} GB/s")

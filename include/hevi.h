@@ -71,9 +71,14 @@ enum {
  * HV_MIXED float32 storage and sweeps / float64 vertical solve and sums. */
 enum { HV_FP64 = 0, HV_FP32 = 1, HV_MIXED = 2 };
 
-/* Device storage order.  HV_KIJ (column-fastest, k + nz*(i + nx*j)) is the
- * layout the kernels are built around; HV_IJK (i-fastest) runs the same
- * kernels with strided column access, for layout comparisons. */
+/* Device storage order (the paper's layout question, Sect. 1.3), each with
+ * its own mapping.  HV_KIJ (column-fastest, k + nz*(i + nx*j)): a column is a
+ * segment of 8/16/32 lanes, each lane owning consecutive levels, the column
+ * solve inside the segment.  HV_IJK (i-fastest, i + nx*(j + ny*k)): one lane
+ * per column, 64 consecutive columns per wavefront, the k loop inside each
+ * lane and a serial Thomas sweep per column (single grids; ensembles, the
+ * Runge-Kutta short step and the damped short step run the column-segment
+ * kernels on this storage, with strided column access). */
 enum { HV_IJK = 0, HV_KIJ = 1 };
 
 /* Short-step integrator.  HV_SHORT_FB: forward-backward HEVI step
@@ -193,24 +198,46 @@ int hv_trace(hv_grid_t g, int32_t on);
 int hv_trace_read(hv_grid_t g, int32_t kind, double *ms_total, int64_t *launches);
 
 /* Autotune: time each kernel kind (slow prep, slow flux, short step) of the
- * loaded state with every launch configuration and keep the fastest; results
- * are bitwise independent of the configuration.  A configuration is a tile
- * shape (16x1, 8x2, 4x4 columns of a 256-thread block) and a block order:
- * launch order, or XCD-chunked (in every group of 64 consecutive tiles,
- * each of the 8 XCDs runs 8 consecutive tiles, so that x-neighbours share
- * its L2; tiles past the last whole group keep launch order).  The choice is appended to
+ * loaded state with every launch configuration and keep the fastest (the
+ * paper's central block-size configuration, Sect. 2.3, made a measurement).
+ * A configuration is a tile shape (16x1, 8x2, 4x4 columns per block), a
+ * block order -- launch order, or XCD-chunked (in every group of 64
+ * consecutive tiles each of the 8 XCDs runs 8 consecutive tiles, so that
+ * x-neighbours share its L2; tiles past the last whole group keep launch
+ * order) -- and the lanes per column (columns per wavefront).  Column-fastest
+ * layout: the default width (32 for float64 storage with 64 levels, else 16)
+ * or the other one (8 lanes for 32 levels, 32 for 64 levels in float32 /
+ * mixed, 16 for 64 levels in float64, 32 for 128 levels).  i-fastest
+ * layout: one lane per column or the default segments.  Configuration index
+ * c = shape + 3 * chunked + 6 * other_width, 0..11 (shape 0..2 for 16x1,
+ * 8x2, 4x4); the damped short step keeps the default.  Tile shape and
+ * block order do not change any
+ * result; neither does the mapping of the slow sweeps; the short step's
+ * mapping sets how its column solve splits into in-lane elimination and
+ * cyclic reduction (or a serial sweep), which changes its rounding
+ * (float64: about 1e-15 relative).  The choice is appended to
  * a plain-text cache ($HV_TUNE_CACHE, else $HOME/.cache/hevi/tune.txt; one
- * line "key c_prep c_flux c_short", c = shape index 0..2 for 16x1, 8x2, 4x4,
- * plus 3 for the XCD-chunked order; the last line of a key wins, and hv_tune
- * rewrites the file with one line per key) that later
- * grids of the same kind read at creation.  tile_x_out (may be NULL)
- * receives the chosen x-extent of the three kinds, negated for the
- * XCD-chunked order.  Synchronises the stream; does not change the state.
+ * line "key c_prep c_flux c_short"; the last line of a key wins, and
+ * hv_tune rewrites the file with one line per key) that later grids of the
+ * same kind read at creation.  tile_x_out and lanes_out (either may be
+ * NULL) receive, per kind, the chosen tile x-extent (negated for the
+ * XCD-chunked order) and lanes per column.  Synchronises the stream; does
+ * not change the state.
  * (Addressing: the slow-flux kernel reaches the arrays of a launch group by
  * 32-bit byte offsets when every member's arrays are under 4 GiB, else by
  * 64-bit addresses; HV_ADDR64=1 in the environment at creation forces the
  * 64-bit form.  Both give bitwise-identical results.) */
-int hv_tune(hv_grid_t g, int32_t *tile_x_out);
+int hv_tune(hv_grid_t g, int32_t *tile_x_out, int32_t *lanes_out);
+
+/* Set the launch configuration of each kernel kind (config[3], indices as
+ * hv_tune numbers them: 0..11 for the column-fastest layout, 0..5 for the
+ * i-fastest one; else HV_ERR_ARG) without timing, e.g. to pin a tuned
+ * choice; config NULL changes nothing.  config_out, tile_x_out and lanes_out
+ * (3 entries each, any may be NULL) receive the configuration in force: its
+ * indices, and the tile x-extents and lanes per column as from hv_tune.
+ * Synchronises the stream. */
+int hv_configure(hv_grid_t g, const int32_t config[3], int32_t *config_out, int32_t *tile_x_out,
+                 int32_t *lanes_out);
 
 /* Lateral and upper damping, the relaxation kernel of the paper's Listing 1
  * (Sect. 2.1), applied after every short step.  The target of each prognostic
@@ -265,9 +292,13 @@ int hv_ens_state_read(hv_ens_t e, int32_t member, int32_t field, double *host_ou
 int hv_ens_mass(hv_ens_t e, int32_t member, double *mass_out, double *energy_out);
 /* As hv_tune, per launch group: members with equal nz and terrain flag,
  * flat groups first, each kind in increasing nz;
- * tile_x_out receives 3 entries per group (room for 18: at most 6 groups),
- * *ngroups_out the group count. */
-int hv_ens_tune(hv_ens_t e, int32_t *tile_x_out, int32_t *ngroups_out);
+ * tile_x_out and lanes_out receive 3 entries per group (room for 18: at
+ * most 6 groups), *ngroups_out the group count (any may be NULL). */
+int hv_ens_tune(hv_ens_t e, int32_t *tile_x_out, int32_t *lanes_out, int32_t *ngroups_out);
+/* As hv_configure, setting launch group `group`; the outputs cover every
+ * group (3 entries per group, room for 18), *ngroups_out the group count. */
+int hv_ens_configure(hv_ens_t e, int32_t group, const int32_t config[3], int32_t *config_out,
+                     int32_t *tile_x_out, int32_t *lanes_out, int32_t *ngroups_out);
 int hv_ens_damping(hv_ens_t e, int32_t member, const double *nu_lat, const double *nu_top,
                    const double *const bnd1[5], const double *const bnd2[5], double t1, double t2,
                    double time_now);

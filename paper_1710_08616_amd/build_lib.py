@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhevi.so")
-SOURCES = [os.path.join(CSRC, "hevi_kernels.hip"), os.path.join(CSRC, "hevi_runtime.cpp")]
+SOURCES = [os.path.join(CSRC, "hevi_kernels.hip"), os.path.join(CSRC, "hevi_columns.hip"),
+           os.path.join(CSRC, "hevi_runtime.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

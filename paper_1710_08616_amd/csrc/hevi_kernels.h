@@ -74,6 +74,9 @@ struct MemberDev {
     const double *nu_top;        // per level (nz)
     void *bnd[2][5];             // boundary states at t1 and t2 (device layout)
     double t1, t2;
+    void *col[4];                // i-fastest layout: the column solve's modified
+                                 // upper diagonal and right-hand side and the
+                                 // rho', Theta' of the W+ = 0 state (solve precision)
 };
 
 // One launch over the blocks of a group of members (all with the same nz).
@@ -93,6 +96,9 @@ struct Group {
     int damp;               // short step: damp the new values (members with damping data)
     int xcd;                // 1: blocks in XCD-chunked order (see block_order)
     int off32;              // 1: every array of every member is under 4 GiB
+    int seg;                // lanes per column (8, 16, 32; 0: the default)
+    int colmap;             // i-fastest layout, one member: one lane per column
+    int nx1, ny1;           // columns of the member when nm == 1
     // sums only (single member): null, or partials in this array and the
     // final sums written to out[slot] (the mass slot with out_add added)
     double *part;
@@ -125,6 +131,10 @@ hipError_t launch_slow_flux(int prec, int layout, int L, const Group &gr, hipStr
 // sums[2] + offset * dt.
 hipError_t launch_short_step(int prec, int layout, int L, const Group &gr, double frac, double offset,
                              hipStream_t s);
+// The one-lane-per-column kernels of the i-fastest layout for a single
+// member (gr.nm == 1, dims gr.nx1 x gr.ny1): kind 0 slow prep, 1 slow flux,
+// 2 forward-backward undamped short step of length (member dt) * frac.
+hipError_t launch_columns(int kind, int prec, const Group &gr, double frac, hipStream_t s);
 // One thread per member of the group: model time += dt (end of a long step).
 hipError_t launch_clock(const Group &gr, hipStream_t s);
 // gr.blk maps blocks to (member, partial).  Sums the perturbation mass

@@ -37,6 +37,7 @@
 //    rho'+ = rho~ - dtau dz(W*),  Theta'+ = Theta~ - dtau dz(thf W*),
 //    W+ = W + dtau (S_W - dz p* - g rho* on faces), which is tridiagonal in W+.
 #include "hevi_kernels.h"
+#include "hevi_device.h"
 
 #include <cstdint>
 #include <mutex>
@@ -47,24 +48,6 @@ namespace {
 
 constexpr int SEG = kSeg;
 constexpr int BLOCK = kBlock;
-
-constexpr double kGamma = 1.4;
-constexpr double kGrav = 9.80665;
-
-template <typename T, int L>
-using vec_t = T __attribute__((ext_vector_type(L)));
-
-// Pointer into device global memory.  Every array a kernel reaches through
-// a member table is global, but the compiler cannot see that through the
-// table and emits flat memory instructions; with the address space explicit
-// it emits global ones, which take a scalar base and a 32-bit per-lane
-// offset.  Which of the two schedules better differs per kernel (measured:
-// the float64 slow flux gains 16% with global instructions, the float32 one
-// loses 13%), so it is a property of the addressing below.
-template <typename T>
-using gptr = T __attribute__((address_space(1))) *;
-
-__device__ __forceinline__ int wrapc(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
 // Block -> (member, tile) -> this segment's column.  A tile is (1 << ti_log2)
 // columns along x by 16 >> ti_log2 along y.
@@ -154,8 +137,6 @@ struct Off32 : Base {
     static constexpr bool kGlobal = G;
 };
 
-// Field f of state buffer b.
-__device__ __forceinline__ void *buf(const MemberDev *m, int b, int f) { return m->st[b][f]; }
 
 // One lane's share of a column: segments of SG lanes per column (16, or 32
 // for the float64-solve short step), lane p owning levels p*L .. p*L+L-1.
@@ -334,54 +315,6 @@ __device__ __forceinline__ void extend2(const T (&x)[L], T (&e)[L + 4], int p, b
     const T topv = zero_top ? T(0) : x[L - 1];
     e[L + 2] = top ? topv : a0;
     e[L + 3] = top ? topv : a1;
-}
-
-template <typename T> __device__ __forceinline__ T xexpm1(T x) { return expm1(x); }
-template <> __device__ __forceinline__ float xexpm1<float>(float x) { return expm1f(x); }
-template <typename T> __device__ __forceinline__ T xlog1p(T x) { return log1p(x); }
-template <> __device__ __forceinline__ float xlog1p<float>(float x) { return log1pf(x); }
-
-// Half the Koren increment, psi(D+/D-) D- / 2, without the division:
-// psi(r) = max(0, min(2r, (1 + 2r)/3, 2))  (Koren 1993, kappa = 1/3).
-// Written sign-symmetrically: with s = sign(D-), a = |D-| and b = s D+,
-//   psi D- / 2 = s max(0, min(b, (a + 2b)/6, a)),
-// and D- = 0 gives 0.  Both signs share one min/max chain, and the halving
-// is folded into exact power-of-two scalings (1/6 = (1/3)/2 exactly), so the
-// value equals q1 + 0.5 * (the two-branch form) bit for bit.
-template <typename T> struct SignBits;
-template <> struct SignBits<float> {
-    using U = unsigned;
-    static constexpr U kSign = 0x80000000u;
-};
-template <> struct SignBits<double> {
-    using U = unsigned long long;
-    static constexpr U kSign = 0x8000000000000000ull;
-};
-
-template <typename T>
-__device__ __forceinline__ T koren_half(T dm, T dp)
-{
-    using U = typename SignBits<T>::U;
-    const U sgn = __builtin_bit_cast(U, dm) & SignBits<T>::kSign;
-    const T a = fabs(dm);
-    const T b = __builtin_bit_cast(T, __builtin_bit_cast(U, dp) ^ sgn);
-    const T t = (a + (b + b)) * T(1.0 / 6.0);
-    const T v = fmax(T(0), fmin(fmin(b, t), a));
-    return __builtin_bit_cast(T, __builtin_bit_cast(U, v) ^ sgn);
-}
-
-// Limited face value between L and R for mass flux m (m >= 0: from L).  The
-// downwind-side differences for m < 0 are the negated upwind ones
-// (x - y = -(y - x) exactly).
-template <typename T>
-__device__ __forceinline__ T kface(T qLL, T qL, T qR, T qRR, T m)
-{
-    const bool up = m >= T(0);
-    const T d1 = qR - qL;
-    const T dm = up ? qL - qLL : -(qRR - qR);
-    const T dp = up ? d1 : -d1;
-    const T q1 = up ? qL : qR;
-    return q1 + koren_half(dm, dp);
 }
 
 // --------------------------------------------------------------------------
@@ -855,29 +788,6 @@ void k_slow_flux(Group gr)
 // short step: horizontally explicit part, then the column solve
 // --------------------------------------------------------------------------
 
-// Reciprocal for the column solve: the hardware estimate refined by Newton
-// steps r <- r + r (1 - x r) (two in float64, one in float32), within an ulp
-// of 1/x for the normal, nonzero pivots a diagonally dominant system has; a
-// correctly rounded division costs about three times as many instructions.
-__device__ __forceinline__ double solve_rcp(double x)
-{
-    double r = __builtin_amdgcn_rcp(x);
-    double e = __builtin_fma(-x, r, 1.0);
-    r = __builtin_fma(r, e, r);
-    e = __builtin_fma(-x, r, 1.0);
-    return __builtin_fma(r, e, r);
-}
-__device__ __forceinline__ float solve_rcp(float x)
-{
-    const float r = __builtin_amdgcn_rcpf(x);
-    const float e = __builtin_fmaf(-x, r, 1.0f);
-    return __builtin_fmaf(r, e, r);
-}
-
-// Solve the segment's tridiagonal system A x_{r-1} + B x_r + C x_{r+1} = D
-// (SG lanes, L >= 2 rows each),
-// one row per level face, lane p holding rows p*L .. p*L+L-1.  A of the
-// first row and C of the last row of the column must be 0.
 // One step of parallel cyclic reduction at distance s: row p (a x_{p-s} +
 // x_p + c x_{p+s} = d, normalised) eliminates its neighbours s rows away.
 template <int s, int SG, bool DPP, typename S>
@@ -899,9 +809,11 @@ __device__ __forceinline__ void pcr_step(int p, S &a, S &c, S &d)
     d = dn;
 }
 
-template <typename S, int L, int SG, bool DPP = (SG == 16)>
-__device__ __forceinline__ void segment_solve(int p, const S (&A)[L], const S (&B)[L],
-                                              const S (&C)[L], const S (&D)[L], S (&x)[L])
+// The rows come from row(l, a, b, c, d), called once per row in the order
+// l = 0 .. L-1 (the lane's last row after the others are eliminated), so a
+// row's coefficients exist only while it is being eliminated.
+template <typename S, int L, int SG, bool DPP = (SG == 16), class Row>
+__device__ __forceinline__ void segment_solve(int p, Row &&row, S (&x)[L])
 {
     // interior rows 0..L-2 in terms of X_{p-1} (last unknown of the lane
     // below) and X_p (this lane's last unknown): x_l = xg + xa X_{p-1} + xb X_p
@@ -909,18 +821,20 @@ __device__ __forceinline__ void segment_solve(int p, const S (&A)[L], const S (&
     S gp[L], yg[L], ya[L], yb[L];
 #pragma unroll
     for (int l = 0; l < n; ++l) {
-        const S den = (l == 0) ? B[0] : B[l] - A[l] * gp[l - 1];
+        S Al, Bl, Cl, Dl;
+        row(l, Al, Bl, Cl, Dl);
+        const S den = (l == 0) ? Bl : Bl - Al * gp[l - 1];
         const S rden = solve_rcp(den);
-        gp[l] = (l < n - 1) ? C[l] * rden : S(0);
-        const S rg = D[l], ra = (l == 0) ? -A[0] : S(0), rb = (l == n - 1) ? -C[l] : S(0);
+        gp[l] = (l < n - 1) ? Cl * rden : S(0);
+        const S rg = Dl, ra = (l == 0) ? -Al : S(0), rb = (l == n - 1) ? -Cl : S(0);
         if (l == 0) {
             yg[0] = rg * rden;
             ya[0] = ra * rden;
             yb[0] = rb * rden;
         } else {
-            yg[l] = (rg - A[l] * yg[l - 1]) * rden;
-            ya[l] = (ra - A[l] * ya[l - 1]) * rden;
-            yb[l] = (rb - A[l] * yb[l - 1]) * rden;
+            yg[l] = (rg - Al * yg[l - 1]) * rden;
+            ya[l] = (ra - Al * ya[l - 1]) * rden;
+            yb[l] = (rb - Al * yb[l - 1]) * rden;
         }
     }
 #pragma unroll
@@ -929,17 +843,19 @@ __device__ __forceinline__ void segment_solve(int p, const S (&A)[L], const S (&
         ya[l] = ya[l] - gp[l] * ya[l + 1];
         yb[l] = yb[l] - gp[l] * yb[l + 1];
     }
+    S AL, BL, CL, DL;
+    row(L - 1, AL, BL, CL, DL);
     // reduced equation of the lane's last row, in X_{p-1}, X_p, X_{p+1}
     const S ga = from_above<SG, DPP>(ya[0]), gb = from_above<SG, DPP>(yb[0]);
     const S gg = from_above<SG, DPP>(yg[0]);
-    const S Ab = A[L - 1] * ya[n - 1];
-    const S Bb = B[L - 1] + A[L - 1] * yb[n - 1] + C[L - 1] * ga;
-    const S Cb = C[L - 1] * gb;
-    const S Db = D[L - 1] - A[L - 1] * yg[n - 1] - C[L - 1] * gg;
+    const S Ab = AL * ya[n - 1];
+    const S Bb = BL + AL * yb[n - 1] + CL * ga;
+    const S Cb = CL * gb;
+    const S Db = DL - AL * yg[n - 1] - CL * gg;
     const S rB = solve_rcp(Bb);
     S a = Ab * rB, c = Cb * rB, d = Db * rB;
     // parallel cyclic reduction over the SG interface rows
-    static_assert(SG == 16 || SG == 32, "16- or 32-lane segments");
+    static_assert(SG == 8 || SG == 16 || SG == 32, "8-, 16- or 32-lane segments");
     if constexpr (DPP) {
         pcr_step<1, SG, true>(p, a, c, d);
         pcr_step<2, SG, true>(p, a, c, d);
@@ -976,12 +892,13 @@ __device__ __forceinline__ void segment_solve(int p, const S (&A)[L], const S (&
 
 // Occupancy target of the short step (waves per SIMD), chosen so that the
 // register budget holds the lane's levels without spilling.  16-lane
-// segments: 4 in float32 (3 with the terrain terms, a separate evaluation
-// state or the damping; 2 with two of them), 2 with a float64 solve (1 for
-// float64 storage with the terrain terms), 1 for 8 levels per lane.  32-lane
-// segments (float64 storage, half the levels per lane): 4 with 2 levels per
-// lane (2 with the damping); with 4, 2 (1 with the terrain terms or the
-// damping).
+// segments: float32 4 (also with the terrain terms or a separate evaluation
+// state; 3 with the damping, 2 with two of them besides the terrain), float32
+// storage with a float64 solve 4 (3 with the terrain terms or a separate
+// evaluation state, 2 with the damping or two extras), 1 for 8 levels per
+// lane.  32-lane segments (float64 storage, half the levels per
+// lane): 4 with 2 levels per lane (2 with the damping); with 4, 2 (1 with
+// the terrain terms or the damping).
 template <typename T, typename S, int L, bool TR, bool EV, int SG, bool DP>
 constexpr int short_waves()
 {
@@ -990,11 +907,14 @@ constexpr int short_waves()
         return (sizeof(T) == 8 && (TR || DP)) ? 1 : 2;
     }
     if (L >= 8) return 1;
+    const int extra = (TR ? 1 : 0) + (EV ? 1 : 0) + (DP ? 1 : 0);
     if (sizeof(T) == 4 && sizeof(S) == 4) {
-        const int extra = (TR ? 1 : 0) + (EV ? 1 : 0) + (DP ? 1 : 0);
-        return extra == 0 ? 4 : (extra == 1 ? 3 : 2);
+        if (extra == 0) return 4;
+        if (!DP) return extra == 1 ? 4 : 3;
+        return extra == 1 ? 3 : 2;
     }
-    if (sizeof(T) == 8 && TR && L >= 4) return 1;
+    if (sizeof(T) == 4) return (DP || extra >= 2) ? 2 : (extra == 0 ? 4 : 3);
+    if (TR && L >= 4) return 1;
     return 2;
 }
 
@@ -1245,9 +1165,8 @@ __device__ __forceinline__ void short_body(
     const S grav = (S)kGrav;
     const int p = ln.p;
     const bool bot = (p == 0), top = (p == SG - 1);
-    // vector loads of the table, except in the flat mixed form (measured:
-    // 1.036 -> 1.108 ms there; FP64 and terrain mixed gain 1.5-2%)
-    constexpr bool kVec = !(sizeof(T) == 4 && sizeof(S) == 8 && !TR);
+    // vector loads of the table (one per lane and field)
+    constexpr bool kVec = true;
     S rdz[L], rdzf[L], av[L], bv[L];
     ln.template vmet<S, kVec>(vm, VM_RDZ, rdz);
     ln.template vmet<S, kVec>(vm, VM_RDZF, rdzf);
@@ -1297,7 +1216,7 @@ __device__ __forceinline__ void short_body(
     Wf[L] = top ? S(0) : (S)w_up;
 
     // the state each cell reaches with W+ = 0
-    S thE[L], rhE[L], pE[L], rEs[L], Cc[L];
+    S thE[L], rhE[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) {
         const S f = one_m_be * dts * rdz[l];
@@ -1308,37 +1227,44 @@ __device__ __forceinline__ void short_body(
             thE[l] = thE[l] + g * (thf[l + 1] * Ef[l + 1] - thf[l] * Ef[l]);
             rhE[l] = rhE[l] + g * (Ef[l + 1] - Ef[l]);
         }
-        Cc[l] = (S)Csc[l];
-        pE[l] = be * ((S)P0c[l] + Cc[l] * thE[l]) + one_m_be * (S)pc[l];
-        rEs[l] = be * rhE[l] + one_m_be * (S)rpold[l];
     }
-    const S C_b = from_below<SG, kMv>(Cc[L - 1]), thf_b = from_below<SG, kMv>(thf[L - 1]);
-    const S pE_b = from_below<SG, kMv>(pE[L - 1]), rEs_b = from_below<SG, kMv>(rEs[L - 1]);
-
-    S A[L], B[L], C[L], D[L];
-#pragma unroll
-    for (int l = 0; l < L; ++l) {
+    // off-centred pressure and density of that state, per level (evaluated
+    // where a row needs them; the lane's top level also for the lane above)
+    auto pE_of = [&](int l) -> S {
+        return be * ((S)P0c[l] + (S)Csc[l] * thE[l]) + one_m_be * (S)pc[l];
+    };
+    auto rEs_of = [&](int l) -> S { return be * rhE[l] + one_m_be * (S)rpold[l]; };
+    S Cm = from_below<SG, kMv>((S)Csc[L - 1]), tfm = from_below<SG, kMv>(thf[L - 1]);
+    S pEm = from_below<SG, kMv>(pE_of(L - 1)), rEm = from_below<SG, kMv>(rEs_of(L - 1));
+    S rdzm = rdz_b;
+    // row l of the tridiagonal system in W+ on level face k0 + l; each call
+    // passes its level's values on as the "below" values of the next row
+    auto row = [&](int l, S &a, S &b, S &c, S &d) {
         const int k = ln.k0 + l;
-        const S Cm = (l == 0) ? C_b : Cc[l - 1];
-        const S tfm = (l == 0) ? thf_b : thf[l - 1];
-        const S pEm = (l == 0) ? pE_b : pE[l - 1];
-        const S rEm = (l == 0) ? rEs_b : rEs[l - 1];
-        const S rdzm = (l == 0) ? rdz_b : rdz[l - 1];
+        const S Cc = (S)Csc[l];
+        const S pE = pE_of(l), rEs = rEs_of(l);
         const S rdzp = rdz[l];
         const S fA = -mu * Cm * tfm * (rdzf[l] * rdzm) + mu * grav * bv[l] * rdzm;
-        const S fC = -mu * Cc[l] * thf[l + 1] * (rdzf[l] * rdzp) - mu * grav * av[l] * rdzp;
-        const S fB = S(1) + mu * thf[l] * (Cc[l] * rdzp + Cm * rdzm) * rdzf[l] +
+        const S fC = -mu * Cc * thf[l + 1] * (rdzf[l] * rdzp) - mu * grav * av[l] * rdzp;
+        const S fB = S(1) + mu * thf[l] * (Cc * rdzp + Cm * rdzm) * rdzf[l] +
                      mu * grav * (av[l] * rdzp - bv[l] * rdzm);
-        const S fD = (S)Wbc[l] + dts * (S)SWc[l] - (dts * rdzf[l]) * (pE[l] - pEm) -
-                     dts * grav * (av[l] * rEs[l] + bv[l] * rEm);
+        const S fD = (S)Wbc[l] + dts * (S)SWc[l] - (dts * rdzf[l]) * (pE - pEm) -
+                     dts * grav * (av[l] * rEs + bv[l] * rEm);
+        // the lid row is (0, 1, 0, 0): chosen by bit masks rather than
+        // selects, which the compiler turns into a divergent branch here
         const bool lid = (k == 0);
-        A[l] = lid ? S(0) : fA;
-        B[l] = lid ? S(1) : fB;
-        C[l] = (lid || k == ln.nz - 1) ? S(0) : fC;
-        D[l] = lid ? S(0) : fD;
-    }
+        a = keep_if(!lid, fA);
+        b = keep_if(!lid, fB) + keep_if(lid, S(1));
+        c = keep_if(!(lid || k == ln.nz - 1), fC);
+        d = keep_if(!lid, fD);
+        Cm = Cc;
+        tfm = thf[l];
+        pEm = pE;
+        rEm = rEs;
+        rdzm = rdzp;
+    };
     S x[L];
-    segment_solve<S, L, SG, kMv>(p, A, B, C, D, x);
+    segment_solve<S, L, SG, kMv>(p, row, x);
 
     const S x_up = from_above<SG, kMv>(x[0]);
     const S xt = top ? S(0) : x_up;
@@ -1636,103 +1562,122 @@ hipError_t dispatch(int prec, int layout, int L, Args &&...args)
     }
 }
 
-// The float64 prep with 4 levels per lane runs in 32-lane segments, as the
-// flux does.
+// Lanes per column (segment width) of a launch.  A column of nz = 16 L
+// levels can run in segments of 16 lanes (L levels per lane), of 32 lanes
+// (L/2 levels, L >= 4) or, for 32 levels, of 8 lanes (4 levels per lane).
+// gr.seg names the width (the autotuner's choice); 0 takes the default: 32
+// lanes for float64 storage with 4 levels per 16 lanes (half the registers
+// per lane, twice the waves per SIMD), else 16.  The other widths are built
+// for the column-fastest layout only, and for the short step not in its
+// damped form, which keep the default.  The slow sweeps compute every cell
+// the same way in any width; the short step's column solve eliminates the
+// lane-interior rows in each lane and the segment's interface rows by
+// cyclic reduction, so its rounding depends on the width.
+template <typename T, int L>
+constexpr int default_seg() { return (sizeof(T) == 8 && L == 4) ? 32 : 16; }
+
+template <int V>
+using ic = std::integral_constant<int, V>;
+
+// go(ic<SG>, ic<levels per lane>) for the launch's width
+template <typename T, int L, bool ALT, class Go>
+hipError_t by_seg(int seg, Go &&go)
+{
+    if (seg == 0 || !ALT) seg = default_seg<T, L>();
+    if constexpr (ALT || default_seg<T, L>() == 16) {
+        if (seg == 16) return go(ic<16>{}, ic<L>{});
+    }
+    if constexpr (L >= 4 && (ALT || default_seg<T, L>() == 32)) {
+        if (seg == 32) return go(ic<32>{}, ic<L / 2>{});
+    }
+    if constexpr (L == 2 && ALT) {
+        if (seg == 8) return go(ic<8>{}, ic<4>{});
+    }
+    return hipErrorInvalidValue;
+}
+
 template <typename T, typename S, class Lay, int L>
 struct RunPrep {
-    static constexpr bool kWide = sizeof(T) == 8 && L == 4;
-    static constexpr int kSG = kWide ? 2 * SEG : SEG;
-    static constexpr int kL = kWide ? L / 2 : L;
     static hipError_t run(const Group &gr, hipStream_t s)
     {
-        if (gr.terrain)
-            hipLaunchKernelGGL((k_slow_prep<T, Lay, kL, true, kSG>), dim3(gr.nblocks), dim3(kColsPerBlock * kSG),
-                               0, s, gr);
-        else
-            hipLaunchKernelGGL((k_slow_prep<T, Lay, kL, false, kSG>), dim3(gr.nblocks), dim3(kColsPerBlock * kSG),
-                               0, s, gr);
-        return hipGetLastError();
+        return by_seg<T, L, Lay::kContig>(gr.seg, [&](auto sg, auto kl) {
+            constexpr int SG = decltype(sg)::value, KL = decltype(kl)::value;
+            if (gr.terrain)
+                hipLaunchKernelGGL((k_slow_prep<T, Lay, KL, true, SG>), dim3(gr.nblocks),
+                                   dim3(kColsPerBlock * SG), 0, s, gr);
+            else
+                hipLaunchKernelGGL((k_slow_prep<T, Lay, KL, false, SG>), dim3(gr.nblocks),
+                                   dim3(kColsPerBlock * SG), 0, s, gr);
+            return hipGetLastError();
+        });
     }
 };
 
-// The float64 flux with 4 levels per lane runs in 32-lane segments (2
-// levels per lane: half the registers per lane, higher occupancy).
 template <typename T, typename S, class Lay, int L>
 struct RunFlux {
-    static constexpr bool kWide = sizeof(T) == 8 && L == 4;
-    static constexpr int kSG = kWide ? 2 * SEG : SEG;
-    static constexpr int kL = kWide ? L / 2 : L;
     template <class A>
-    static void go(const Group &gr, hipStream_t s)
+    static hipError_t go(const Group &gr, hipStream_t s)
     {
-        if (gr.terrain)
-            hipLaunchKernelGGL((k_slow_flux<T, A, kL, true, kSG>), dim3(gr.nblocks), dim3(kColsPerBlock * kSG),
-                               0, s, gr);
-        else
-            hipLaunchKernelGGL((k_slow_flux<T, A, kL, false, kSG>), dim3(gr.nblocks), dim3(kColsPerBlock * kSG),
-                               0, s, gr);
+        return by_seg<T, L, Lay::kContig>(gr.seg, [&](auto sg, auto kl) {
+            constexpr int SG = decltype(sg)::value, KL = decltype(kl)::value;
+            if (gr.terrain)
+                hipLaunchKernelGGL((k_slow_flux<T, A, KL, true, SG>), dim3(gr.nblocks),
+                                   dim3(kColsPerBlock * SG), 0, s, gr);
+            else
+                hipLaunchKernelGGL((k_slow_flux<T, A, KL, false, SG>), dim3(gr.nblocks),
+                                   dim3(kColsPerBlock * SG), 0, s, gr);
+            return hipGetLastError();
+        });
     }
     // The slow flux is instruction-heavy enough that 32-bit array offsets pay
     // (float32: 0.973 -> 0.895 ms, float64: 2.50 -> 2.09 ms on 1024x1024x64);
     // the host selects them when every array fits in 4 GiB.
     static hipError_t run(const Group &gr, hipStream_t s)
     {
-        if (gr.off32) go<Off32<Lay, sizeof(T) == 8>>(gr, s);
-        else go<Lay>(gr, s);
-        return hipGetLastError();
+        if (gr.off32) return go<Off32<Lay, sizeof(T) == 8>>(gr, s);
+        return go<Lay>(gr, s);
     }
 };
 
-// The float64 short step uses 32-lane segments (half the levels per lane,
-// so twice the waves per SIMD) for 64-level columns; with 128 levels a
-// 512-thread block cannot go below 2 waves per SIMD, whose 256 registers do
-// not hold 4 float64 levels per lane, so those keep 16 lanes.  The
-// mixed form keeps 16 lanes: with 2 levels per lane the cyclic reduction's
-// float64 work per level doubles and outweighs the higher occupancy
-// (measured on 1024x1024x64: 1.035 ms with 16 lanes, 1.109 ms with 32).
+// The mixed form keeps 16 lanes by default: with 2 levels per lane the
+// cyclic reduction's float64 work per level doubles and outweighs the higher
+// occupancy (measured on 1024x1024x64: 1.035 ms with 16 lanes, 1.109 ms with
+// 32).
 template <typename T, typename S, class Lay, int L>
 struct RunShort {
-    static constexpr bool kWide = sizeof(T) == 8 && L == 4;
-    static constexpr int kSG = kWide ? 2 * SEG : SEG;
-    static constexpr int kL = kWide ? L / 2 : L;
     template <class A, bool TR, bool EV, bool DP>
-    static void launch(const Group &gr, double frac, double offset, hipStream_t s)
+    static hipError_t launch(const Group &gr, double frac, double offset, hipStream_t s)
     {
-        hipLaunchKernelGGL((k_short_step<T, S, A, kL, TR, EV, kSG, DP>), dim3(gr.nblocks),
-                           dim3(kColsPerBlock * kSG), 0, s, gr, frac, offset);
+        return by_seg<T, L, Lay::kContig && !DP>(gr.seg, [&](auto sg, auto kl) {
+            constexpr int SG = decltype(sg)::value, KL = decltype(kl)::value;
+            hipLaunchKernelGGL((k_short_step<T, S, A, KL, TR, EV, SG, DP>), dim3(gr.nblocks),
+                               dim3(kColsPerBlock * SG), 0, s, gr, frac, offset);
+            return hipGetLastError();
+        });
     }
     // 32-bit offsets with global instructions pay in the flat, undamped
     // float32 step only (measured on 1024 x 1024 x 64: 0.895 -> 0.876 ms;
     // the Runge-Kutta pair unchanged; the float64-solve form loses 4%, the
     // terrain form 5%, the damped form 4%)
     template <bool TR, bool EV, bool DP>
-    static void go(const Group &gr, double frac, double offset, hipStream_t s)
+    static hipError_t go(const Group &gr, double frac, double offset, hipStream_t s)
     {
-        if constexpr (std::is_same_v<S, float> && !TR && !DP) {
-            if (gr.off32) {
-                launch<Off32<Lay, true>, TR, EV, DP>(gr, frac, offset, s);
-                return;
-            }
+        if constexpr (sizeof(T) == 4 && !TR && !DP) {
+            if (gr.off32) return launch<Off32<Lay, true>, TR, EV, DP>(gr, frac, offset, s);
         }
-        launch<Lay, TR, EV, DP>(gr, frac, offset, s);
+        return launch<Lay, TR, EV, DP>(gr, frac, offset, s);
     }
     template <bool TR, bool EV>
-    static void go2(const Group &gr, double frac, double offset, hipStream_t s)
+    static hipError_t go2(const Group &gr, double frac, double offset, hipStream_t s)
     {
-        if (gr.damp) go<TR, EV, true>(gr, frac, offset, s);
-        else go<TR, EV, false>(gr, frac, offset, s);
+        if (gr.damp) return go<TR, EV, true>(gr, frac, offset, s);
+        return go<TR, EV, false>(gr, frac, offset, s);
     }
     static hipError_t run(const Group &gr, double frac, double offset, hipStream_t s)
     {
         const bool ev = gr.ev != gr.src;
-        if (gr.terrain) {
-            if (ev) go2<true, true>(gr, frac, offset, s);
-            else go2<true, false>(gr, frac, offset, s);
-        } else {
-            if (ev) go2<false, true>(gr, frac, offset, s);
-            else go2<false, false>(gr, frac, offset, s);
-        }
-        return hipGetLastError();
+        if (gr.terrain) return ev ? go2<true, true>(gr, frac, offset, s) : go2<true, false>(gr, frac, offset, s);
+        return ev ? go2<false, true>(gr, frac, offset, s) : go2<false, false>(gr, frac, offset, s);
     }
 };
 
@@ -1759,17 +1704,23 @@ struct RunSums {
 
 hipError_t launch_slow_prep(int prec, int layout, int L, const Group &gr, hipStream_t s)
 {
+    if (gr.colmap && layout == 0) return launch_columns(0, prec, gr, 0.0, s);
     return dispatch<RunPrep>(prec, layout, L, gr, s);
 }
 
 hipError_t launch_slow_flux(int prec, int layout, int L, const Group &gr, hipStream_t s)
 {
+    if (gr.colmap && layout == 0) return launch_columns(1, prec, gr, 0.0, s);
     return dispatch<RunFlux>(prec, layout, L, gr, s);
 }
 
 hipError_t launch_short_step(int prec, int layout, int L, const Group &gr, double frac, double offset,
                              hipStream_t s)
 {
+    // the column kernel takes the forward-backward step without damping; the
+    // Runge-Kutta and damped forms run in column segments
+    if (gr.colmap && layout == 0 && !gr.damp && gr.ev == gr.src)
+        return launch_columns(2, prec, gr, frac, s);
     return dispatch<RunShort>(prec, layout, L, gr, frac, offset, s);
 }
 

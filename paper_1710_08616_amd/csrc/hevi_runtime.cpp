@@ -42,10 +42,14 @@ constexpr double kDefaultDriftBound = 1e-9;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // tile shapes the autotuner tries: log2 of the columns along x (16x1, 8x2, 4x4);
-// a launch configuration is a shape and a block order (launch order or
-// XCD-chunked): index c = shape + 3 * chunked, c in 0..5
+// a launch configuration is a shape, a block order (launch order or
+// XCD-chunked) and a column width: index c = shape + 3 * chunked + 6 * w,
+// c in 0..11.  Column-fastest layout: w = 0 the default lanes per column,
+// w = 1 the other width (see alt_seg).  i-fastest layout: w = 0 one lane per
+// column (64 columns per wavefront; single grids), w = 1 column segments of
+// the default width.
 constexpr int kShapes[3] = {4, 3, 2};
-constexpr int kConfigs = 6;
+constexpr int kConfigs = 12;
 enum { KIND_PREP = 0, KIND_FLUX = 1, KIND_SHORT = 2, NKIND = 3 };
 
 struct MemberHost {
@@ -168,6 +172,7 @@ bool unsupported(const hv_grid_desc *d, std::string *why)
 }
 
 size_t elem_size(int prec) { return prec == HV_FP64 ? 8 : 4; }
+size_t solve_size(int prec) { return prec == HV_FP32 ? 4 : 8; }   // column-solve values
 
 struct Carve {
     size_t off = 0;
@@ -235,6 +240,8 @@ Plan make_plan(int n, const hv_grid_desc *d)
             for (int a = 0; a < 4; ++a) c.take(ncell * es);
             c.take(sizeof(double) * hv::GEO_NFIELDS * (size_t)d[q].nx * d[q].ny);
         }
+        if (d[q].layout == HV_IJK && n == 1)   // one-lane-per-column solve (single grids)
+            for (int a = 0; a < 4; ++a) c.take(ncell * solve_size(d[q].precision));
         c.take(hv::vm_bytes(d[q].nz));
         c.take(sizeof(double) * (size_t)hv::partials_of(d[q].nx, d[q].ny));
         c.take(sizeof(double) * hv::kSums);
@@ -383,6 +390,19 @@ void fill_geo(const MemberHost &m, std::vector<double> &geo)
 
 hipError_t sync(hv_ens *e) { return hipStreamSynchronize(e->stream); }
 
+// Lanes per column: the default (32 for float64 storage with 64 levels,
+// else 16) and the other width the kernels offer for the column-fastest
+// layout (8 lanes for 32 levels, 32 for 64 levels in float32, 16 for 64
+// levels in float64, 32 for 128 levels).
+int default_seg(int prec, int L) { return (prec == HV_FP64 && L == 4) ? 32 : 16; }
+int alt_seg(int prec, int L)
+{
+    if (L == 2) return 8;
+    if (L == 4) return default_seg(prec, L) == 32 ? 16 : 32;
+    return 32;
+}
+int configs_of(const hv_ens *) { return kConfigs; }
+
 // Launch description of group g for a kernel kind (< 0: the sums); ev < 0
 // means the short step takes its explicit terms from src.
 hv::Group group_launch(const hv_ens *e, const GroupHost &g, int kind, int src, int dst = 0,
@@ -406,9 +426,21 @@ hv::Group group_launch(const hv_ens *e, const GroupHost &g, int kind, int src, i
         gr.blk = g.d_blk[sh];
         gr.nblocks = g.nblocks[sh];
         gr.ti_log2 = kShapes[sh];
-        gr.xcd = g.shape[kind] / 3;
+        gr.xcd = (g.shape[kind] / 3) % 2;
+        const bool w = g.shape[kind] / 6;
+        const bool col = !w;
+        if (e->layout == HV_KIJ) {
+            gr.seg = w ? alt_seg(e->prec, g.L) : 0;
+        } else {
+            // one lane per column for a single grid (whose workspace holds the
+            // column solve's arrays); the Runge-Kutta short step keeps its
+            // column segments (both of its stages alike)
+            gr.colmap = (col && e->n == 1 && !(kind == KIND_SHORT && e->rk2)) ? 1 : 0;
+        }
     }
     gr.first = g.ids[0];
+    gr.nx1 = e->m[g.ids[0]].nx;
+    gr.ny1 = e->m[g.ids[0]].ny;
     return gr;
 }
 
@@ -548,7 +580,7 @@ std::string tune_key(const hv_ens *e, const GroupHost &g)
     return k.str();
 }
 
-bool cache_lookup(const std::string &key, int shape[NKIND])
+bool cache_lookup(const std::string &key, int shape[NKIND], int nconf)
 {
     const std::string path = cache_path();
     if (path.empty()) return false;
@@ -557,7 +589,7 @@ bool cache_lookup(const std::string &key, int shape[NKIND])
     int a, b, c;
     bool found = false;
     while (f >> k >> a >> b >> c)
-        if (k == key && a >= 0 && a < kConfigs && b >= 0 && b < kConfigs && c >= 0 && c < kConfigs) {
+        if (k == key && a >= 0 && a < nconf && b >= 0 && b < nconf && c >= 0 && c < nconf) {
             shape[0] = a; shape[1] = b; shape[2] = c;
             found = true;
         }
@@ -669,6 +701,8 @@ int ens_create(hv_ens *e, int n, const hv_grid_desc *descs, void *ws, size_t byt
             if (r == hipSuccess) r = sync(e);
             if (r != hipSuccess) return hip_fail(nullptr, r, "upload geometry");
         }
+        for (int a = 0; a < 4; ++a)
+            v.col[a] = (e->layout == HV_IJK && n == 1) ? base + c.take(m.ncell * solve_size(e->prec)) : nullptr;
         v.vm = (const double *)(base + c.take(hv::vm_bytes(m.nz)));
         v.partials = (double *)(base + c.take(sizeof(double) * (size_t)v.npart));
         v.sums = (double *)(base + c.take(sizeof(double) * hv::kSums));
@@ -718,7 +752,7 @@ int ens_create(hv_ens *e, int n, const hv_grid_desc *descs, void *ws, size_t byt
         if (r == hipSuccess) r = sync(e);
         if (r != hipSuccess) return hip_fail(nullptr, r, "upload group tables");
         int shape[NKIND];
-        if (cache_lookup(tune_key(e, g), shape)) std::copy(shape, shape + NKIND, g.shape);
+        if (cache_lookup(tune_key(e, g), shape, configs_of(e))) std::copy(shape, shape + NKIND, g.shape);
     }
     std::vector<hv::MemberDev> table(n);
     for (int q = 0; q < n; ++q) table[q] = e->m[q].dev;
@@ -1039,8 +1073,28 @@ int member_damping(hv_ens *e, int q, const double *nu_lat, const double *nu_top,
     return HV_OK;
 }
 
+// Per group and kernel kind: the tile x-extent (negative for the
+// XCD-chunked order) and the lanes per column of its configuration.
+void report_configs(const hv_ens *e, int32_t *tiles, int32_t *lanes, int32_t *ngroups,
+                    int32_t *configs = nullptr)
+{
+    if (ngroups) *ngroups = (int32_t)e->groups.size();
+    for (size_t gi = 0; gi < e->groups.size(); ++gi)
+        for (int k = 0; k < NKIND; ++k) {
+            const GroupHost &g = e->groups[gi];
+            const int c = g.shape[k];
+            if (configs) configs[gi * NKIND + k] = c;
+            if (tiles) tiles[gi * NKIND + k] = ((c / 3) % 2 ? -1 : 1) * (1 << kShapes[c % 3]);
+            int n = c / 6 ? alt_seg(e->prec, g.L) : default_seg(e->prec, g.L);
+            if (e->layout == HV_IJK)
+                n = (!(c / 6) && e->n == 1 && !(k == KIND_SHORT && e->rk2)) ? 1
+                                                                                    : default_seg(e->prec, g.L);
+            if (lanes) lanes[gi * NKIND + k] = n;
+        }
+}
+
 // Time one kernel kind of one group in every launch configuration; keep the fastest.
-int tune(hv_ens *e, int32_t *out, int32_t *ngroups)
+int tune(hv_ens *e, int32_t *out, int32_t *lanes, int32_t *ngroups)
 {
     for (int q = 0; q < e->n; ++q)
         if (!e->m[q].have_state) return fail(e, HV_ERR_STATE, "tune before every member's state_init");
@@ -1064,10 +1118,11 @@ int tune(hv_ens *e, int32_t *out, int32_t *ngroups)
         for (int kind = 0; kind < NKIND && rc == HV_OK; ++kind) {
             // two interleaved rounds, the faster of each configuration's two
             // timings counts (one round alone let run-to-run noise decide)
+            const int nconf = configs_of(e);
             float t[kConfigs];
             std::fill(t, t + kConfigs, 1e30f);
-            for (int it = 0; it < 2 * kConfigs && rc == HV_OK; ++it) {
-                const int s = it % kConfigs;
+            for (int it = 0; it < 2 * nconf && rc == HV_OK; ++it) {
+                const int s = it % nconf;
                 g.shape[kind] = s;
                 // the slow arrays the flux and short step read must hold this stage's values
                 if ((r = launch(g, KIND_PREP, e->stream)) != hipSuccess ||
@@ -1083,7 +1138,7 @@ int tune(hv_ens *e, int32_t *out, int32_t *ngroups)
                 if (r != hipSuccess) { rc = hip_fail(e, r, "tune"); break; }
                 t[s] = std::min(t[s], ms);
             }
-            g.shape[kind] = (int)(std::min_element(t, t + kConfigs) - t);
+            g.shape[kind] = (int)(std::min_element(t, t + nconf) - t);
         }
         if (rc != HV_OK) break;
         cache_store(tune_key(e, g), g.shape);
@@ -1093,13 +1148,23 @@ int tune(hv_ens *e, int32_t *out, int32_t *ngroups)
     e->tracing = was_tracing;
     if (rc != HV_OK) return rc;
     drop_graphs(e);
-    if (ngroups) *ngroups = (int32_t)e->groups.size();
-    if (out)
-        for (size_t gi = 0; gi < e->groups.size(); ++gi)
-            for (int k = 0; k < NKIND; ++k) {
-                const int c = e->groups[gi].shape[k];
-                out[gi * NKIND + k] = (c / 3 ? -1 : 1) * (1 << kShapes[c % 3]);
-            }
+    report_configs(e, out, lanes, ngroups);
+    return HV_OK;
+}
+
+// Set the launch configurations of group gi (config[k] per kernel kind, as
+// the tuner numbers them).
+int configure(hv_ens *e, int gi, const int32_t *config)
+{
+    if (gi < 0 || gi >= (int)e->groups.size()) return fail(e, HV_ERR_ARG, "group index out of range");
+    if (!config) return fail(e, HV_ERR_ARG, "config is NULL");
+    for (int k = 0; k < NKIND; ++k)
+        if (config[k] < 0 || config[k] >= configs_of(e))
+            return fail(e, HV_ERR_ARG, "configuration index out of range");
+    hipError_t r = sync(e);   // running steps use the current graphs
+    if (r != hipSuccess) return hip_fail(e, r, "stream synchronize");
+    for (int k = 0; k < NKIND; ++k) e->groups[gi].shape[k] = config[k];
+    drop_graphs(e);
     return HV_OK;
 }
 
@@ -1200,10 +1265,22 @@ int hv_mass_noalloc(hv_grid_t g, double *dev_out)
     return HV_OK;
 }
 
-int hv_tune(hv_grid_t g, int32_t *tile_x_out)
+int hv_tune(hv_grid_t g, int32_t *tile_x_out, int32_t *lanes_out)
 {
     if (!g) return fail(nullptr, HV_ERR_ARG, "handle is NULL");
-    return tune(g, tile_x_out, nullptr);
+    return tune(g, tile_x_out, lanes_out, nullptr);
+}
+
+int hv_configure(hv_grid_t g, const int32_t config[3], int32_t *config_out, int32_t *tile_x_out,
+                 int32_t *lanes_out)
+{
+    if (!g) return fail(nullptr, HV_ERR_ARG, "handle is NULL");
+    if (config) {
+        const int rc = configure(g, 0, config);
+        if (rc != HV_OK) return rc;
+    }
+    report_configs(g, tile_x_out, lanes_out, nullptr, config_out);
+    return HV_OK;
 }
 
 int hv_damping(hv_grid_t g, const double *nu_lat, const double *nu_top,
@@ -1285,10 +1362,22 @@ int hv_ens_mass(hv_ens_t e, int32_t member, double *mass_out, double *energy_out
     return member_mass(e, member, mass_out, energy_out);
 }
 
-int hv_ens_tune(hv_ens_t e, int32_t *tile_x_out, int32_t *ngroups_out)
+int hv_ens_tune(hv_ens_t e, int32_t *tile_x_out, int32_t *lanes_out, int32_t *ngroups_out)
 {
     if (!e) return fail(nullptr, HV_ERR_ARG, "handle is NULL");
-    return tune(e, tile_x_out, ngroups_out);
+    return tune(e, tile_x_out, lanes_out, ngroups_out);
+}
+
+int hv_ens_configure(hv_ens_t e, int32_t group, const int32_t config[3], int32_t *config_out,
+                     int32_t *tile_x_out, int32_t *lanes_out, int32_t *ngroups_out)
+{
+    if (!e) return fail(nullptr, HV_ERR_ARG, "handle is NULL");
+    if (config) {
+        const int rc = configure(e, group, config);
+        if (rc != HV_OK) return rc;
+    }
+    report_configs(e, tile_x_out, lanes_out, ngroups_out, config_out);
+    return HV_OK;
 }
 
 int hv_ens_damping(hv_ens_t e, int32_t member, const double *nu_lat, const double *nu_top,

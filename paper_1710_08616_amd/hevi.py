@@ -31,7 +31,8 @@ EXPORTS = ("hv_workspace_bytes", "hv_grid_create", "hv_state_init", "hv_step", "
            "hv_mass", "hv_tune", "hv_trace", "hv_trace_read", "hv_grid_destroy", "hv_last_error",
            "hv_ens_workspace_bytes", "hv_ens_create", "hv_ens_state_init", "hv_ens_step",
            "hv_ens_state_read", "hv_ens_mass", "hv_ens_tune", "hv_ens_trace", "hv_ens_trace_read",
-           "hv_ens_destroy", "hv_ens_last_error", "hv_diffuse", "hv_damping", "hv_ens_damping", "hv_mass_noalloc")
+           "hv_ens_destroy", "hv_ens_last_error", "hv_diffuse", "hv_damping", "hv_ens_damping", "hv_mass_noalloc", "hv_configure",
+           "hv_ens_configure")
 K_SLOW_PREP, K_SLOW_FLUX, K_SHORT_STEP, K_MASS = 0, 1, 2, 3
 KERNEL_KINDS = {"slow_prep": K_SLOW_PREP, "slow_flux": K_SLOW_FLUX, "short_step": K_SHORT_STEP,
                 "mass": K_MASS}
@@ -90,8 +91,13 @@ def load():
     L.hv_trace_read.restype = ctypes.c_int
     L.hv_trace_read.argtypes = [ctypes.c_void_p, ctypes.c_int32, _dp,
                                 ctypes.POINTER(ctypes.c_int64)]
+    _ip = ctypes.POINTER(ctypes.c_int32)
     L.hv_tune.restype = ctypes.c_int
-    L.hv_tune.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]
+    L.hv_tune.argtypes = [ctypes.c_void_p, _ip, _ip]
+    L.hv_configure.restype = ctypes.c_int
+    L.hv_configure.argtypes = [ctypes.c_void_p, _ip, _ip, _ip, _ip]
+    L.hv_ens_configure.restype = ctypes.c_int
+    L.hv_ens_configure.argtypes = [ctypes.c_void_p, ctypes.c_int32, _ip, _ip, _ip, _ip, _ip]
     L.hv_ens_workspace_bytes.restype = ctypes.c_size_t
     L.hv_ens_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.POINTER(GridDesc)]
     L.hv_ens_create.restype = ctypes.c_int
@@ -107,8 +113,7 @@ def load():
     L.hv_ens_mass.restype = ctypes.c_int
     L.hv_ens_mass.argtypes = [ctypes.c_void_p, ctypes.c_int32, _dp, _dp]
     L.hv_ens_tune.restype = ctypes.c_int
-    L.hv_ens_tune.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
-                              ctypes.POINTER(ctypes.c_int32)]
+    L.hv_ens_tune.argtypes = [ctypes.c_void_p, _ip, _ip, _ip]
     L.hv_ens_trace.restype = ctypes.c_int
     L.hv_ens_trace.argtypes = [ctypes.c_void_p, ctypes.c_int32]
     L.hv_ens_trace_read.restype = ctypes.c_int
@@ -267,10 +272,27 @@ class Domain:
     def tune(self):
         """Autotune the launch configurations; returns the chosen tile x-extent
         per kernel kind (slow prep, slow flux, short step), negative where the
-        XCD-chunked block order won."""
+        XCD-chunked block order won, and the lanes per column of each kind."""
         out = (ctypes.c_int32 * 3)()
-        self._check(load().hv_tune(self.handle, out))
-        return list(out)
+        lanes = (ctypes.c_int32 * 3)()
+        self._check(load().hv_tune(self.handle, out, lanes))
+        return list(out), list(lanes)
+
+    def configure(self, config=None):
+        """hv_configure: set (config = 3 indices) and/or report the launch
+        configurations in force, as (indices, tile x-extents, lanes per column)."""
+        idx = (ctypes.c_int32 * 3)()
+        out = (ctypes.c_int32 * 3)()
+        lanes = (ctypes.c_int32 * 3)()
+        cfg = None if config is None else (ctypes.c_int32 * 3)(*[int(c) for c in config])
+        self._check(load().hv_configure(self.handle, cfg, idx, out, lanes))
+        return list(idx), list(out), list(lanes)
+
+    def pin_default_short_width(self):
+        """Keep the tuned tiles and block orders but the short step's default
+        lanes per column (whose column solve rounds like an untuned run)."""
+        idx, _t, _l = self.configure()
+        self.configure([idx[0], idx[1], idx[2] % 6])
 
     def trace(self, on: bool):
         return self._check(load().hv_trace(self.handle, 1 if on else 0))
@@ -381,12 +403,34 @@ class Ensemble:
         return (m.value, e.value) if energy else m.value
 
     def tune(self):
-        """Autotune per launch group; returns [prep, flux, short] tile x-extents
-        per group (at most 6 groups: flat and terrain, nz = 32, 64, 128)."""
+        """Autotune per launch group; returns per group (at most 6: flat and
+        terrain, nz = 32, 64, 128) the [prep, flux, short] tile x-extents and
+        lanes per column."""
         out = (ctypes.c_int32 * (3 * 6))()
+        lanes = (ctypes.c_int32 * (3 * 6))()
         ng = ctypes.c_int32()
-        self._check(load().hv_ens_tune(self.handle, out, ctypes.byref(ng)))
-        return [list(out[3 * g:3 * g + 3]) for g in range(ng.value)]
+        self._check(load().hv_ens_tune(self.handle, out, lanes, ctypes.byref(ng)))
+        return [(list(out[3 * g:3 * g + 3]), list(lanes[3 * g:3 * g + 3])) for g in range(ng.value)]
+
+    def configure(self, group=0, config=None):
+        """hv_ens_configure for one launch group; returns every group's
+        (indices, tile x-extents, lanes per column)."""
+        idx = (ctypes.c_int32 * (3 * 6))()
+        out = (ctypes.c_int32 * (3 * 6))()
+        lanes = (ctypes.c_int32 * (3 * 6))()
+        ng = ctypes.c_int32()
+        cfg = None if config is None else (ctypes.c_int32 * 3)(*[int(c) for c in config])
+        self._check(load().hv_ens_configure(self.handle, int(group), cfg, idx, out, lanes,
+                                            ctypes.byref(ng)))
+        return [(list(idx[3 * g:3 * g + 3]), list(out[3 * g:3 * g + 3]), list(lanes[3 * g:3 * g + 3]))
+                for g in range(ng.value)]
+
+    def pin_default_short_width(self):
+        """Keep every group's tuned tiles and block orders but the short
+        step's default lanes per column (whose column solve rounds like an
+        untuned run)."""
+        for g, (idx, _t, _l) in enumerate(self.configure()):
+            self.configure(g, [idx[0], idx[1], idx[2] % 6])
 
     def trace(self, on: bool):
         return self._check(load().hv_ens_trace(self.handle, 1 if on else 0))

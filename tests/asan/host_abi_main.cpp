@@ -114,7 +114,8 @@ int main()
     CHECK(hv_state_read(nullptr, 0, &x) == HV_ERR_ARG);
     CHECK(hv_mass(nullptr, &x, &x) == HV_ERR_ARG);
     CHECK(hv_mass_noalloc(nullptr, &x) == HV_ERR_ARG);
-    CHECK(hv_tune(nullptr, nullptr) == HV_ERR_ARG);
+    CHECK(hv_tune(nullptr, nullptr, nullptr) == HV_ERR_ARG);
+    CHECK(hv_configure(nullptr, nullptr, nullptr, nullptr, nullptr) == HV_ERR_ARG);
     CHECK(hv_trace(nullptr, 1) == HV_ERR_ARG);
     CHECK(hv_state_init(nullptr, nullptr, nullptr, nullptr, nullptr) == HV_ERR_ARG);
     hv_grid_destroy(nullptr);

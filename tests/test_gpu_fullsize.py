@@ -11,7 +11,10 @@ are then exactly the full-domain values and are compared with the GPU run of
 the whole domain, in the launch configuration the benchmark times.
 
 Samples: the domain corner (periodic wrap on both axes), the strongest
-bubble, and over terrain the highest point of the orography.
+bubble, and over terrain the highest point of the orography.  The
+2048x2048x64 domain over hills runs in both storage orders, each in its
+own mapping (16-lane column segments for the column-fastest order, one lane
+per column for the i-fastest one).
 """
 import numpy as np
 import pytest
@@ -65,9 +68,9 @@ def _samples(s):
     return pts
 
 
-def _check(hv, oracle, s, prec):
-    print(f"case: full {s.name} {s.nx}x{s.ny}x{s.nz} {prec}: gpu step", flush=True)
-    d = hv.Domain(s, precision=prec, layout="kij")
+def _check(hv, oracle, s, prec, layout="kij"):
+    print(f"case: full {s.name} {s.nx}x{s.ny}x{s.nz} {prec} {layout}: gpu step", flush=True)
+    d = hv.Domain(s, precision=prec, layout=layout)
     # the benchmark autotunes before it times; so does this run (the tuner
     # leaves the state as it was)
     print(f"case: full {s.name} {prec}: tuned launch configurations {d.tune()}", flush=True)
@@ -112,3 +115,13 @@ def test_large_workload_sampled_columns_match_oracle(hv, oracle, large, prec):
 @pytest.mark.parametrize("prec", ["mixed"])
 def test_terrain_workload_sampled_columns_match_oracle(hv, oracle, terrain, prec):
     _check(hv, oracle, terrain, prec)
+
+
+@pytest.fixture(scope="module")
+def xl():
+    return inputs.workload("xl")
+
+
+@pytest.mark.parametrize("layout", ["kij", "ijk"])
+def test_xl_workload_sampled_columns_match_oracle_in_both_layouts(hv, oracle, xl, layout):
+    _check(hv, oracle, xl, "fp32", layout)

@@ -210,8 +210,11 @@ int hv_trace_read(hv_grid_t g, int32_t kind, double *ms_total, int64_t *launches
  * mixed, 16 for 64 levels in float64, 32 for 128 levels).  i-fastest
  * layout: one lane per column or the default segments.  Configuration index
  * c = shape + 3 * chunked + 6 * other_width, 0..11 (shape 0..2 for 16x1,
- * 8x2, 4x4); the damped short step keeps the default.  Tile shape and
- * block order do not change any
+ * 8x2, 4x4); the damped short step keeps the default.  The column-fastest
+ * slow flux has 12 more, c + 12: the same with each segment walking a run of
+ * 8 columns along x, carrying the flux through the face it shares with the
+ * next column (a block then spans 8 times the tile's columns along x).
+ * Tile shape, block order and runs do not change any
  * result; neither does the mapping of the slow sweeps; the short step's
  * mapping sets how its column solve splits into in-lane elimination and
  * cyclic reduction (or a serial sweep), which changes its rounding
@@ -230,8 +233,8 @@ int hv_trace_read(hv_grid_t g, int32_t kind, double *ms_total, int64_t *launches
 int hv_tune(hv_grid_t g, int32_t *tile_x_out, int32_t *lanes_out);
 
 /* Set the launch configuration of each kernel kind (config[3], indices as
- * hv_tune numbers them: 0..11 for the column-fastest layout, 0..5 for the
- * i-fastest one; else HV_ERR_ARG) without timing, e.g. to pin a tuned
+ * hv_tune numbers them: 0..11, and 0..23 for the column-fastest slow flux;
+ * else HV_ERR_ARG) without timing, e.g. to pin a tuned
  * choice; config NULL changes nothing.  config_out, tile_x_out and lanes_out
  * (3 entries each, any may be NULL) receive the configuration in force: its
  * indices, and the tile x-extents and lanes per column as from hv_tune.

@@ -36,6 +36,10 @@ template <> __device__ __forceinline__ float xexpm1<float>(float x) { return exp
 template <typename T> __device__ __forceinline__ T xlog1p(T x) { return log1p(x); }
 template <> __device__ __forceinline__ float xlog1p<float>(float x) { return log1pf(x); }
 
+// a * b + c with one rounding
+__device__ __forceinline__ double xfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float xfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // Half the Koren increment, psi(D+/D-) D- / 2, without the division:
 // psi(r) = max(0, min(2r, (1 + 2r)/3, 2))  (Koren 1993, kappa = 1/3).
 // Written sign-symmetrically: with s = sign(D-), a = |D-| and b = s D+,
@@ -60,7 +64,8 @@ __device__ __forceinline__ T koren_half(T dm, T dp)
     const U sgn = __builtin_bit_cast(U, dm) & SignBits<T>::kSign;
     const T a = fabs(dm);
     const T b = __builtin_bit_cast(T, __builtin_bit_cast(U, dp) ^ sgn);
-    const T t = (a + (b + b)) * T(1.0 / 6.0);
+    // a + 2b in one rounding (2b is exact), as a + (b + b) rounds it
+    const T t = xfma(b, T(2), a) * T(1.0 / 6.0);
     const T v = fmax(T(0), fmin(fmin(b, t), a));
     return __builtin_bit_cast(T, __builtin_bit_cast(U, v) ^ sgn);
 }

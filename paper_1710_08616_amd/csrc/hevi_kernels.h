@@ -99,6 +99,9 @@ struct Group {
     int seg;                // lanes per column (8, 16, 32; 0: the default)
     int colmap;             // i-fastest layout, one member: one lane per column
     int nx1, ny1;           // columns of the member when nm == 1
+    int run;                // slow flux, column-fastest layout: > 1 = columns per
+                            // segment run along x (blocks cover runs, see
+                            // tiles_of_run); else one column per segment
     // sums only (single member): null, or partials in this array and the
     // final sums written to out[slot] (the mass slot with out_add added)
     double *part;
@@ -114,6 +117,13 @@ inline int tiles_of(int nx, int ny, int ti_log2)
 {
     const int ti = 1 << ti_log2, tj = kColsPerBlock >> ti_log2;
     return ((nx + ti - 1) / ti) * ((ny + tj - 1) / tj);
+}
+// Blocks a member needs for a tile shape whose columns along x are runs of
+// run columns each.
+inline int tiles_of_run(int nx, int ny, int ti_log2, int run)
+{
+    const int span = (1 << ti_log2) * run, tj = kColsPerBlock >> ti_log2;
+    return ((nx + span - 1) / span) * ((ny + tj - 1) / tj);
 }
 inline int partials_of(int nx, int ny)
 {

@@ -785,6 +785,339 @@ void k_slow_flux(Group gr)
 }
 
 // --------------------------------------------------------------------------
+// slow sweep, part 2, in runs along x
+// --------------------------------------------------------------------------
+// Each x-face is shared by two columns: above, both evaluate it, so the Koren
+// value and mass flux of every x-face (one of a cell's five faces, for each
+// of the four tendencies) is computed twice, and every column loads its four
+// x-neighbours of each advected quantity.  Here a segment walks a run of
+// gr.run consecutive columns along x and carries over, in registers, the
+// flux through the face it shares with the next column, the x-window of the
+// four advected quantities and the mass-flux operands of that face: a column
+// loads one new x-neighbour per quantity.  Every face flux takes the same
+// operands in the same order as above, so the tendencies are bitwise equal.
+// A block covers (1 << ti_log2) runs along x by 16 >> ti_log2 rows.
+template <int SG>
+__device__ __forceinline__ Where locate_run(const Group &gr)
+{
+    Where w;
+    const int b = block_order(gr);
+    int t = b, id = gr.first;
+    if (gr.nm > 1) {
+        const unsigned v = gr.blk[b];
+        t = (int)(v & 0xFFFFFFu);
+        id = (int)(v >> 24);
+    }
+    w.m = gr.mem + id;
+    const int ti = 1 << gr.ti_log2, tj = kColsPerBlock >> gr.ti_log2;
+    const int span = ti * gr.run;
+    const int tiles_x = (w.m->nx + span - 1) / span;
+    const int c = (int)threadIdx.x / SG;
+    w.i = (t % tiles_x) * span + (c & (ti - 1)) * gr.run;
+    w.j = (t / tiles_x) * tj + (c >> gr.ti_log2);
+    w.active = w.i < w.m->nx && w.j < w.m->ny;
+    return w;
+}
+
+template <typename T, class Lay, int L, bool TR, int SG>
+__global__ __launch_bounds__(kColsPerBlock * SG)
+void k_slow_flux_run(Group gr)
+{
+    const Where wh = locate_run<SG>(gr);
+    if (!wh.active) return;
+    const MemberDev *m = wh.m;
+    Lane<Lay, L, SG> ln(m->nx, m->ny, m->nz, wh.i, wh.j);
+    const double *__restrict__ vm = m->vm;
+    const double *__restrict__ geo = m->geo;
+    const T rdx = (T)m->rdx, rdy = (T)m->rdy;
+    const T *__restrict__ U = (const T *)buf(m, gr.src, 1);
+    const T *__restrict__ V = (const T *)buf(m, gr.src, 2);
+    const T *__restrict__ Wz = TR ? (const T *)m->spec[3] : (const T *)buf(m, gr.src, 3);
+    const T *__restrict__ uu = (const T *)m->spec[0];
+    const T *__restrict__ vv = (const T *)m->spec[1];
+    const T *__restrict__ ww = (const T *)m->spec[2];
+    const T *__restrict__ th = (const T *)m->slow[4];
+    T *__restrict__ SU = (T *)m->slow[0];
+    T *__restrict__ SV = (T *)m->slow[1];
+    T *__restrict__ SW = (T *)m->slow[2];
+    T *__restrict__ RT = (T *)m->slow[3];
+    const int iend = min(wh.i + gr.run, m->nx);
+    const bool top = (ln.p == SG - 1);
+
+    // per-level constants of the lane's levels
+    T rdz[L], rdzf[L], a[L], b[L];
+    ln.template vmet<T, TR>(vm, VM_RDZ, rdz);
+    ln.template vmet<T, TR>(vm, VM_RDZF, rdzf);
+    ln.template vmet<T, TR>(vm, VM_A, a);
+    ln.template vmet<T, TR>(vm, VM_B, b);
+
+    // Carried from column i-1 to column i: the x-windows q(i-1), q(i),
+    // q(i+1) of u, v, w, theta (slot 3 takes q(i+2)); the fluxes through the
+    // face i-1/2; U(i, j), V(i-1, j), V(i-1, j+1), Wz(i-1, j) and over
+    // terrain the face Jacobians of those points.
+    T uw[4][L], vw[4][L], wq[4][L], tw[4][L];
+    T fxU[L], fxV[L], fxW[L], fxT[L];
+    T Uc[L], Vw0[L], Vw1[L], Wl[L];
+    T ju_c = T(1), jvw0 = T(1), jvw1 = T(1);
+    {
+        // the face i0-1/2, as column i0 - 1 evaluates it as its east face
+        T Ul[L], Usc[L], q0[L];
+        T jus_c = T(1);
+        ln.load(U, -1, 0, Ul);
+        ln.load(U, 0, 0, Uc);
+        ln.load(U, 0, -1, Usc);
+        ln.load(V, -1, 0, Vw0);
+        ln.load(V, -1, 1, Vw1);
+        ln.load(Wz, -1, 0, Wl);
+        T jul = T(1);
+        if constexpr (TR) {
+            jul = (T)ln.geo(geo, GEO_JU, -1, 0);
+            ju_c = (T)ln.geo(geo, GEO_JU, 0, 0);
+            jus_c = (T)ln.geo(geo, GEO_JU, 0, -1);
+            jvw0 = (T)ln.geo(geo, GEO_JV, -1, 0);
+            jvw1 = (T)ln.geo(geo, GEO_JV, -1, 1);
+        }
+        const T Ucb = from_below<SG>(Uc[L - 1]);
+        ln.load(uu, -2, 0, q0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) ln.load(uu, d - 1, 0, uw[d]);
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            const T mx = TR ? T(0.5) * (jul * Ul[l] + ju_c * Uc[l]) : T(0.5) * (Ul[l] + Uc[l]);
+            fxU[l] = mx * kface(q0[l], uw[0][l], uw[1][l], uw[2][l], mx);
+        }
+        ln.load(vv, -2, 0, q0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) ln.load(vv, d - 1, 0, vw[d]);
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            const T mx = TR ? T(0.5) * (jus_c * Usc[l] + ju_c * Uc[l]) : T(0.5) * (Usc[l] + Uc[l]);
+            fxV[l] = mx * kface(q0[l], vw[0][l], vw[1][l], vw[2][l], mx);
+        }
+        ln.load(ww, -2, 0, q0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) ln.load(ww, d - 1, 0, wq[d]);
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            const T ub = (l == 0) ? Ucb : Uc[l - 1];
+            const T mx = TR ? T(0.5) * (ju_c * ub + ju_c * Uc[l]) : T(0.5) * (ub + Uc[l]);
+            fxW[l] = mx * kface(q0[l], wq[0][l], wq[1][l], wq[2][l], mx);
+        }
+        ln.load(th, -2, 0, q0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) ln.load(th, d - 1, 0, tw[d]);
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            const T mx = TR ? ju_c * Uc[l] : Uc[l];
+            fxT[l] = mx * (kface(q0[l], tw[0][l], tw[1][l], tw[2][l], mx) -
+                           T(0.5) * (tw[0][l] + tw[1][l]));
+        }
+    }
+
+    for (int i = wh.i; i < iend; ++i) {
+        ln.i = i;
+        T Up[L], Usp[L], V00[L], V01[L], Vm[L], W0[L], Wsm[L];
+        ln.load(uu, 2, 0, uw[3]);
+        ln.load(vv, 2, 0, vw[3]);
+        ln.load(ww, 2, 0, wq[3]);
+        ln.load(th, 2, 0, tw[3]);
+        ln.load(U, 1, 0, Up);
+        ln.load(U, 1, -1, Usp);
+        ln.load(V, 0, 0, V00);
+        ln.load(V, 0, 1, V01);
+        ln.load(V, 0, -1, Vm);
+        ln.load(Wz, 0, 0, W0);
+        ln.load(Wz, 0, -1, Wsm);
+        T jup = T(1), jusp = T(1), jv00 = T(1), jv01 = T(1), jvm = T(1), jc = T(1);
+        if constexpr (TR) {
+            jup = (T)ln.geo(geo, GEO_JU, 1, 0);
+            jusp = (T)ln.geo(geo, GEO_JU, 1, -1);
+            jv00 = (T)ln.geo(geo, GEO_JV, 0, 0);
+            jv01 = (T)ln.geo(geo, GEO_JV, 0, 1);
+            jvm = (T)ln.geo(geo, GEO_JV, 0, -1);
+            jc = (T)ln.geo(geo, GEO_J, 0, 0);
+        }
+        // S_U
+        {
+            T qy[4][L], e[L + 4], fz[L + 1], out[L];
+            ln.load(uu, 0, -2, qy[0]);
+            ln.load(uu, 0, -1, qy[1]);
+            ln.load(uu, 0, 1, qy[2]);
+            ln.load(uu, 0, 2, qy[3]);
+            extend2<SG>(uw[1], e, ln.p, false);
+#pragma unroll
+            for (int l = 0; l < L; ++l) {
+                const T mz = T(0.5) * (Wl[l] + W0[l]);
+                const T q = kface(e[l], e[l + 1], e[l + 2], e[l + 3], mz);
+                fz[l] = (ln.k0 + l == 0) ? T(0) : mz * q;
+            }
+            const T fz_a = from_above<SG>(fz[0]);
+            fz[L] = top ? T(0) : fz_a;
+#pragma unroll
+            for (int l = 0; l < L; ++l) {
+                T m1, n0, n1;
+                if constexpr (TR) {
+                    m1 = T(0.5) * (ju_c * Uc[l] + jup * Up[l]);
+                    n0 = T(0.5) * (jvw0 * Vw0[l] + jv00 * V00[l]);
+                    n1 = T(0.5) * (jvw1 * Vw1[l] + jv01 * V01[l]);
+                } else {
+                    m1 = T(0.5) * (Uc[l] + Up[l]);
+                    n0 = T(0.5) * (Vw0[l] + V00[l]);
+                    n1 = T(0.5) * (Vw1[l] + V01[l]);
+                }
+                const T fx1 = m1 * kface(uw[0][l], uw[1][l], uw[2][l], uw[3][l], m1);
+                const T fy0 = n0 * kface(qy[0][l], qy[1][l], uw[1][l], qy[2][l], n0);
+                const T fy1 = n1 * kface(qy[1][l], uw[1][l], qy[2][l], qy[3][l], n1);
+                const T sum = (fx1 - fxU[l]) * rdx + (fy1 - fy0) * rdy + (fz[l + 1] - fz[l]) * rdz[l];
+                if constexpr (TR) out[l] = -sum / ju_c;
+                else out[l] = -sum;
+                fxU[l] = fx1;
+            }
+            ln.store(SU, out);
+        }
+        // S_V
+        {
+            T qy[4][L], e[L + 4], fz[L + 1], out[L];
+            ln.load(vv, 0, -2, qy[0]);
+            ln.load(vv, 0, -1, qy[1]);
+            ln.load(vv, 0, 1, qy[2]);
+            ln.load(vv, 0, 2, qy[3]);
+            extend2<SG>(vw[1], e, ln.p, false);
+#pragma unroll
+            for (int l = 0; l < L; ++l) {
+                const T mz = T(0.5) * (Wsm[l] + W0[l]);
+                const T q = kface(e[l], e[l + 1], e[l + 2], e[l + 3], mz);
+                fz[l] = (ln.k0 + l == 0) ? T(0) : mz * q;
+            }
+            const T fz_a = from_above<SG>(fz[0]);
+            fz[L] = top ? T(0) : fz_a;
+#pragma unroll
+            for (int l = 0; l < L; ++l) {
+                T m1, n0, n1;
+                if constexpr (TR) {
+                    m1 = T(0.5) * (jusp * Usp[l] + jup * Up[l]);
+                    n0 = T(0.5) * (jvm * Vm[l] + jv00 * V00[l]);
+                    n1 = T(0.5) * (jv00 * V00[l] + jv01 * V01[l]);
+                } else {
+                    m1 = T(0.5) * (Usp[l] + Up[l]);
+                    n0 = T(0.5) * (Vm[l] + V00[l]);
+                    n1 = T(0.5) * (V00[l] + V01[l]);
+                }
+                const T fx1 = m1 * kface(vw[0][l], vw[1][l], vw[2][l], vw[3][l], m1);
+                const T fy0 = n0 * kface(qy[0][l], qy[1][l], vw[1][l], qy[2][l], n0);
+                const T fy1 = n1 * kface(qy[1][l], vw[1][l], qy[2][l], qy[3][l], n1);
+                const T sum = (fx1 - fxV[l]) * rdx + (fy1 - fy0) * rdy + (fz[l + 1] - fz[l]) * rdz[l];
+                if constexpr (TR) out[l] = -sum / jv00;
+                else out[l] = -sum;
+                fxV[l] = fx1;
+            }
+            ln.store(SV, out);
+        }
+        // S_W (level faces; face 0 is the lower lid)
+        {
+            T qy[4][L], e[L + 4], We[L + 4], fz[L + 1], out[L];
+            ln.load(ww, 0, -2, qy[0]);
+            ln.load(ww, 0, -1, qy[1]);
+            ln.load(ww, 0, 1, qy[2]);
+            ln.load(ww, 0, 2, qy[3]);
+            const T U1b = from_below<SG>(Up[L - 1]);
+            const T V0b = from_below<SG>(V00[L - 1]), V1b = from_below<SG>(V01[L - 1]);
+            extend2<SG>(wq[1], e, ln.p, true);
+            extend2<SG>(W0, We, ln.p, true);
+#pragma unroll
+            for (int l = 1; l <= L; ++l) {
+                const T mz = T(0.5) * (We[l + 1] + We[l + 2]);
+                fz[l] = mz * kface(e[l], e[l + 1], e[l + 2], e[l + 3], mz);
+            }
+            fz[0] = from_below<SG>(fz[L]);
+#pragma unroll
+            for (int l = 0; l < L; ++l) {
+                const int k = ln.k0 + l;
+                const T u1b = (l == 0) ? U1b : Up[l - 1];
+                const T v0b = (l == 0) ? V0b : V00[l - 1];
+                const T v1b = (l == 0) ? V1b : V01[l - 1];
+                T m1, n0, n1;
+                if constexpr (TR) {
+                    m1 = T(0.5) * (jup * u1b + jup * Up[l]);
+                    n0 = T(0.5) * (jv00 * v0b + jv00 * V00[l]);
+                    n1 = T(0.5) * (jv01 * v1b + jv01 * V01[l]);
+                } else {
+                    m1 = T(0.5) * (u1b + Up[l]);
+                    n0 = T(0.5) * (v0b + V00[l]);
+                    n1 = T(0.5) * (v1b + V01[l]);
+                }
+                const T fx1 = m1 * kface(wq[0][l], wq[1][l], wq[2][l], wq[3][l], m1);
+                const T fy0 = n0 * kface(qy[0][l], qy[1][l], wq[1][l], qy[2][l], n0);
+                const T fy1 = n1 * kface(qy[1][l], wq[1][l], qy[2][l], qy[3][l], n1);
+                const T sum = (fx1 - fxW[l]) * rdx + (fy1 - fy0) * rdy + (fz[l + 1] - fz[l]) * rdzf[l];
+                T sw;
+                if constexpr (TR) sw = -sum / jc;
+                else sw = -sum;
+                out[l] = (k == 0) ? T(0) : sw;
+                fxW[l] = fx1;
+            }
+            ln.store(SW, out);
+        }
+        // R_Theta
+        {
+            T qy[4][L], e[L + 4], gz[L + 1], out[L];
+            ln.load(th, 0, -2, qy[0]);
+            ln.load(th, 0, -1, qy[1]);
+            ln.load(th, 0, 1, qy[2]);
+            ln.load(th, 0, 2, qy[3]);
+            extend2<SG>(tw[1], e, ln.p, false);
+#pragma unroll
+            for (int l = 0; l < L; ++l) {
+                const T mz = W0[l];
+                const T tl = kface(e[l], e[l + 1], e[l + 2], e[l + 3], mz);
+                const T tcen = a[l] * e[l + 2] + b[l] * e[l + 1];
+                gz[l] = (ln.k0 + l == 0) ? T(0) : mz * (tl - tcen);
+            }
+            const T gz_a = from_above<SG>(gz[0]);
+            gz[L] = top ? T(0) : gz_a;
+#pragma unroll
+            for (int l = 0; l < L; ++l) {
+                T m1 = Up[l], n0 = V00[l], n1 = V01[l];
+                if constexpr (TR) {
+                    m1 = jup * m1;
+                    n0 = jv00 * n0;
+                    n1 = jv01 * n1;
+                }
+                const T g1 = m1 * (kface(tw[0][l], tw[1][l], tw[2][l], tw[3][l], m1) -
+                                   T(0.5) * (tw[1][l] + tw[2][l]));
+                const T h0 = n0 * (kface(qy[0][l], qy[1][l], tw[1][l], qy[2][l], n0) -
+                                   T(0.5) * (qy[1][l] + tw[1][l]));
+                const T h1 = n1 * (kface(qy[1][l], tw[1][l], qy[2][l], qy[3][l], n1) -
+                                   T(0.5) * (tw[1][l] + qy[2][l]));
+                const T sum = (g1 - fxT[l]) * rdx + (h1 - h0) * rdy + (gz[l + 1] - gz[l]) * rdz[l];
+                if constexpr (TR) out[l] = -sum / jc;
+                else out[l] = -sum;
+                fxT[l] = g1;
+            }
+            ln.store(RT, out);
+        }
+        // slide the windows to column i + 1
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                uw[d][l] = uw[d + 1][l];
+                vw[d][l] = vw[d + 1][l];
+                wq[d][l] = wq[d + 1][l];
+                tw[d][l] = tw[d + 1][l];
+            }
+            Uc[l] = Up[l];
+            Vw0[l] = V00[l];
+            Vw1[l] = V01[l];
+            Wl[l] = W0[l];
+        }
+        ju_c = jup;
+        jvw0 = jv00;
+        jvw1 = jv01;
+    }
+}
+
+// --------------------------------------------------------------------------
 // short step: horizontally explicit part, then the column solve
 // --------------------------------------------------------------------------
 
@@ -1620,6 +1953,17 @@ struct RunFlux {
     {
         return by_seg<T, L, Lay::kContig>(gr.seg, [&](auto sg, auto kl) {
             constexpr int SG = decltype(sg)::value, KL = decltype(kl)::value;
+            if constexpr (Lay::kContig) {
+                if (gr.run > 1) {
+                    if (gr.terrain)
+                        hipLaunchKernelGGL((k_slow_flux_run<T, A, KL, true, SG>), dim3(gr.nblocks),
+                                           dim3(kColsPerBlock * SG), 0, s, gr);
+                    else
+                        hipLaunchKernelGGL((k_slow_flux_run<T, A, KL, false, SG>), dim3(gr.nblocks),
+                                           dim3(kColsPerBlock * SG), 0, s, gr);
+                    return hipGetLastError();
+                }
+            }
             if (gr.terrain)
                 hipLaunchKernelGGL((k_slow_flux<T, A, KL, true, SG>), dim3(gr.nblocks),
                                    dim3(kColsPerBlock * SG), 0, s, gr);

@@ -47,9 +47,12 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 // c in 0..11.  Column-fastest layout: w = 0 the default lanes per column,
 // w = 1 the other width (see alt_seg).  i-fastest layout: w = 0 one lane per
 // column (64 columns per wavefront; single grids), w = 1 column segments of
-// the default width.
+// the default width.  The column-fastest slow flux has 12 more, c + 12: the
+// same with every segment walking a run of kRun columns along x (a block
+// then covers kRun times the tile's columns along x).
 constexpr int kShapes[3] = {4, 3, 2};
-constexpr int kConfigs = 12;
+constexpr int kConfigs = 24;   // most configurations of a kind
+constexpr int kRun = 8;
 enum { KIND_PREP = 0, KIND_FLUX = 1, KIND_SHORT = 2, NKIND = 3 };
 
 struct MemberHost {
@@ -72,9 +75,11 @@ struct GroupHost {
     bool off32 = false;        // every member's arrays fit 32-bit byte offsets
     std::vector<int> ids;
     int *d_ids = nullptr;
-    unsigned *d_blk[3] = {};   // per tile shape: block -> slot << 24 | tile (nm > 1)
+    // per tile shape, then per tile shape of runs (kRun columns per segment
+    // along x): block -> slot << 24 | tile (nm > 1)
+    unsigned *d_blk[6] = {};
     unsigned *d_pblk = nullptr;  // block -> slot << 24 | partial (nm > 1)
-    int nblocks[3] = {};
+    int nblocks[6] = {};
     int npblocks = 0;
     int shape[NKIND] = {0, 0, 0};  // launch configuration per kernel kind (0..kConfigs-1)
 };
@@ -197,8 +202,9 @@ size_t group_words(const std::vector<int> &ids, const hv_grid_desc *d)
 {
     size_t w = ids.size();
     if (ids.size() > 1) {
-        for (int s = 0; s < 3; ++s)
-            for (int q : ids) w += (size_t)hv::tiles_of(d[q].nx, d[q].ny, kShapes[s]);
+        for (int s = 0; s < 6; ++s)
+            for (int q : ids)
+                w += (size_t)hv::tiles_of_run(d[q].nx, d[q].ny, kShapes[s % 3], s < 3 ? 1 : kRun);
         for (int q : ids) w += (size_t)hv::partials_of(d[q].nx, d[q].ny);
     }
     return w;
@@ -401,7 +407,11 @@ int alt_seg(int prec, int L)
     if (L == 4) return default_seg(prec, L) == 32 ? 16 : 32;
     return 32;
 }
-int configs_of(const hv_ens *) { return kConfigs; }
+// configurations of a kernel kind (runs: the column-fastest slow flux)
+int configs_of(const hv_ens *e, int kind)
+{
+    return (kind == KIND_FLUX && e->layout == HV_KIJ) ? 24 : 12;
+}
 
 // Launch description of group g for a kernel kind (< 0: the sums); ev < 0
 // means the short step takes its explicit terms from src.
@@ -422,12 +432,13 @@ hv::Group group_launch(const hv_ens *e, const GroupHost &g, int kind, int src, i
         gr.nblocks = g.npblocks;
         gr.ti_log2 = 4;
     } else {
-        const int sh = g.shape[kind] % 3;
-        gr.blk = g.d_blk[sh];
-        gr.nblocks = g.nblocks[sh];
+        const int sh = g.shape[kind] % 3, run = g.shape[kind] / 12;
+        gr.blk = g.d_blk[sh + 3 * run];
+        gr.nblocks = g.nblocks[sh + 3 * run];
         gr.ti_log2 = kShapes[sh];
         gr.xcd = (g.shape[kind] / 3) % 2;
-        const bool w = g.shape[kind] / 6;
+        gr.run = run ? kRun : 0;
+        const bool w = (g.shape[kind] / 6) % 2;
         const bool col = !w;
         if (e->layout == HV_KIJ) {
             gr.seg = w ? alt_seg(e->prec, g.L) : 0;
@@ -729,11 +740,12 @@ int ens_create(hv_ens *e, int n, const hv_grid_desc *descs, void *ws, size_t byt
         h.reserve(group_words(g.ids, descs));
         for (int a = 0; a < nm; ++a) h.push_back((unsigned)g.ids[a]);
         g.d_ids = dst;
-        for (int sh = 0; sh < 3; ++sh) {
+        for (int sh = 0; sh < 6; ++sh) {
             g.nblocks[sh] = 0;
             if (nm > 1) g.d_blk[sh] = (unsigned *)dst + h.size();
             for (int a = 0; a < nm; ++a) {
-                const int nt = hv::tiles_of(e->m[g.ids[a]].nx, e->m[g.ids[a]].ny, kShapes[sh]);
+                const int nt = hv::tiles_of_run(e->m[g.ids[a]].nx, e->m[g.ids[a]].ny, kShapes[sh % 3],
+                                                sh < 3 ? 1 : kRun);
                 if (nt >= (1 << 24)) return fail(nullptr, HV_ERR_ARG, "member too large");
                 if (nm > 1)
                     for (int t = 0; t < nt; ++t) h.push_back(((unsigned)g.ids[a] << 24) | (unsigned)t);
@@ -752,7 +764,9 @@ int ens_create(hv_ens *e, int n, const hv_grid_desc *descs, void *ws, size_t byt
         if (r == hipSuccess) r = sync(e);
         if (r != hipSuccess) return hip_fail(nullptr, r, "upload group tables");
         int shape[NKIND];
-        if (cache_lookup(tune_key(e, g), shape, configs_of(e))) std::copy(shape, shape + NKIND, g.shape);
+        if (cache_lookup(tune_key(e, g), shape, kConfigs) && shape[KIND_PREP] < configs_of(e, KIND_PREP) &&
+            shape[KIND_FLUX] < configs_of(e, KIND_FLUX) && shape[KIND_SHORT] < configs_of(e, KIND_SHORT))
+            std::copy(shape, shape + NKIND, g.shape);
     }
     std::vector<hv::MemberDev> table(n);
     for (int q = 0; q < n; ++q) table[q] = e->m[q].dev;
@@ -1084,11 +1098,12 @@ void report_configs(const hv_ens *e, int32_t *tiles, int32_t *lanes, int32_t *ng
             const GroupHost &g = e->groups[gi];
             const int c = g.shape[k];
             if (configs) configs[gi * NKIND + k] = c;
-            if (tiles) tiles[gi * NKIND + k] = ((c / 3) % 2 ? -1 : 1) * (1 << kShapes[c % 3]);
-            int n = c / 6 ? alt_seg(e->prec, g.L) : default_seg(e->prec, g.L);
+            if (tiles)
+                tiles[gi * NKIND + k] = ((c / 3) % 2 ? -1 : 1) * (1 << kShapes[c % 3]) * (c / 12 ? kRun : 1);
+            const bool w = (c / 6) % 2;
+            int n = w ? alt_seg(e->prec, g.L) : default_seg(e->prec, g.L);
             if (e->layout == HV_IJK)
-                n = (!(c / 6) && e->n == 1 && !(k == KIND_SHORT && e->rk2)) ? 1
-                                                                                    : default_seg(e->prec, g.L);
+                n = (!w && e->n == 1 && !(k == KIND_SHORT && e->rk2)) ? 1 : default_seg(e->prec, g.L);
             if (lanes) lanes[gi * NKIND + k] = n;
         }
 }
@@ -1118,7 +1133,7 @@ int tune(hv_ens *e, int32_t *out, int32_t *lanes, int32_t *ngroups)
         for (int kind = 0; kind < NKIND && rc == HV_OK; ++kind) {
             // two interleaved rounds, the faster of each configuration's two
             // timings counts (one round alone let run-to-run noise decide)
-            const int nconf = configs_of(e);
+            const int nconf = configs_of(e, kind);
             float t[kConfigs];
             std::fill(t, t + kConfigs, 1e30f);
             for (int it = 0; it < 2 * nconf && rc == HV_OK; ++it) {
@@ -1159,7 +1174,7 @@ int configure(hv_ens *e, int gi, const int32_t *config)
     if (gi < 0 || gi >= (int)e->groups.size()) return fail(e, HV_ERR_ARG, "group index out of range");
     if (!config) return fail(e, HV_ERR_ARG, "config is NULL");
     for (int k = 0; k < NKIND; ++k)
-        if (config[k] < 0 || config[k] >= configs_of(e))
+        if (config[k] < 0 || config[k] >= configs_of(e, k))
             return fail(e, HV_ERR_ARG, "configuration index out of range");
     hipError_t r = sync(e);   // running steps use the current graphs
     if (r != hipSuccess) return hip_fail(e, r, "stream synchronize");

@@ -76,7 +76,9 @@ def test_tuned_tile_shapes_give_identical_results(hv, tmp_path, monkeypatch):
     e0.close()
     e1 = hv.Ensemble(ms, precision="fp32")
     shapes = e1.tune()
-    assert len(shapes) == 2 and all(abs(x) in (16, 8, 4) for tiles, _ in shapes for x in tiles)
+    # tile x-extents: 16, 8 or 4 columns, or as many runs of 8 columns (slow flux)
+    assert len(shapes) == 2 and all(abs(x) in (16, 8, 4, 128, 64, 32)
+                                    for tiles, _ in shapes for x in tiles)
     assert all(n in (8, 16, 32) for _, lanes in shapes for n in lanes)
     # the short step's width changes its rounding; every other choice is bitwise
     e1.pin_default_short_width()
@@ -90,11 +92,12 @@ def test_tuned_tile_shapes_give_identical_results(hv, tmp_path, monkeypatch):
 
 def test_every_launch_configuration_is_bitwise(hv, tmp_path, monkeypatch):
     """Each launch configuration of the slow sweeps (three tile shapes, launch
-    order or XCD-chunked order, 16 or 8 lanes per column) and each of the
-    short step's six at its default width, forced through the tune cache read
-    at creation, gives the untuned result bitwise.  90 16x1 tiles (75 8x2,
-    80 4x4): the chunked order deals 64 of them and leaves the rest in launch
-    order; two members make it the grouped form."""
+    order or XCD-chunked order, 16 or 8 lanes per column; for the flux also
+    in runs of 8 columns along x) and each of the short step's six at its
+    default width, forced through the tune cache read at creation, gives the
+    untuned result bitwise.  90 16x1 tiles (75 8x2, 80 4x4): the chunked
+    order deals 64 of them and leaves the rest in launch order; two members
+    make it the grouped form."""
     cache = tmp_path / "tune.txt"
     monkeypatch.setenv("HV_TUNE_CACHE", str(cache))
     ms = [inputs.make_state(40, 30, 32, seed=31, dt=8.0, n_short=3, noise=0.4, u_bg=6.0),
@@ -107,9 +110,9 @@ def test_every_launch_configuration_is_bitwise(hv, tmp_path, monkeypatch):
         base.tune()
         base.close()
         key = cache.read_text().split()[-4]
-        for c in range(12):
+        for c in range(24):
             with open(cache, "a") as f:
-                f.write(f"{key} {c} {(c + 2) % 12} {(c + 4) % 6}\n")
+                f.write(f"{key} {c % 12} {(c + 2) % 24} {(c + 4) % 6}\n")
             e = hv.Ensemble(group, precision="mixed")
             e.step(2, 3)
             for q in range(len(group)):

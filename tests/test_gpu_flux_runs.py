@@ -1,0 +1,89 @@
+"""The slow flux in runs along x (hv_configure flux configurations 12..23,
+column-fastest layout): every segment walks 8 consecutive columns and
+carries the flux through the face it shares with the next column, with the
+x-window of the advected quantities, instead of evaluating both x-faces of
+every column.  Each face flux takes the same operands in the same order as
+in the one-column-per-segment kernel, so whole steps are bitwise equal to
+that kernel's, in every tile shape, block order and width: flat and over
+hills, 32/64/128 levels, three precisions, grids whose nx is not a multiple
+of a block's span (runs cut at the east edge), a grid narrower than one run
+(its window wraps onto itself), and the grouped launch of an ensemble.
+"""
+import numpy as np
+import pytest
+
+from paper_1710_08616_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hv():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1710_08616_amd import hevi
+    hevi.load()
+    return hevi
+
+
+def _state(nx, ny, nz, terrain, seed):
+    h = None
+    if terrain:
+        h = inputs.orography(nx, ny, 2000.0, 2000.0, seed, hmax=1200.0, hills=2,
+                             smin=3000.0 * max(1, nx // 20), smax=6000.0 * max(1, nx // 20))
+    return inputs.make_state(nx, ny, nz, seed=seed, terrain=h, noise=0.5, u_bg=6.0, v_bg=-2.0,
+                             shear=8.0, n_short=3,
+                             bubbles=[(nx * 1000.0, ny * 1000.0, 5000.0, 4000.0)])
+
+
+def _run(hv, s, prec, config, n_long=2):
+    d = hv.Domain(s, precision=prec)
+    idx, tiles, _lanes = d.configure(config)
+    assert list(idx) == list(config)
+    d.step(s.dt, n_long, s.n_short)
+    out = d.read_all()
+    d.close()
+    return out, tiles
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
+@pytest.mark.parametrize("nz", [32, 64, 128])
+@pytest.mark.parametrize("terrain", [False, True])
+def test_flux_in_runs_is_bitwise_equal(hv, prec, nz, terrain):
+    s = _state(37, 21, nz, terrain, seed=60 + nz)
+    print(f"case: flux runs {prec} nz={nz} terrain={terrain}", flush=True)
+    # (per-column flux, flux in runs): 4x4 chunked, 16x1 launch order, 8x2 in the other width
+    for base_c, run_c in ((5, 17), (0, 12), (10, 22)):
+        ref, t0 = _run(hv, s, prec, [5, base_c, 5])
+        got, t1 = _run(hv, s, prec, [5, run_c, 5])
+        assert abs(t1[1]) == 8 * abs(t0[1])
+        for name, a, b in zip(inputs.FIELD_NAMES, got, ref):
+            assert np.array_equal(a, b), (name, base_c, run_c)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_flux_in_runs_on_a_grid_narrower_than_a_run(hv, prec):
+    """nx = 5: each run holds the whole row and its x-window wraps."""
+    s = _state(5, 7, 64, False, seed=71)
+    print(f"case: flux runs narrow {prec}", flush=True)
+    ref, _ = _run(hv, s, prec, [0, 2, 0], n_long=3)
+    got, _ = _run(hv, s, prec, [0, 14, 0], n_long=3)
+    for name, a, b in zip(inputs.FIELD_NAMES, got, ref):
+        assert np.array_equal(a, b), name
+
+
+def test_flux_in_runs_in_an_ensemble(hv):
+    ms = [_state(37, 21, 64, False, seed=81), _state(20, 30, 64, False, seed=82),
+          _state(24, 16, 64, True, seed=83)]
+    print("case: flux runs ensemble", flush=True)
+    out = {}
+    for c in (3, 15):
+        e = hv.Ensemble(ms, precision="mixed")
+        for g in range(2):
+            e.configure(g, [3, c, 3])
+        e.step(2, 3)
+        out[c] = [e.read_all(q) for q in range(len(ms))]
+        e.close()
+    for q in range(len(ms)):
+        for name, a, b in zip(inputs.FIELD_NAMES, out[15][q], out[3][q]):
+            assert np.array_equal(a, b), (q, name)

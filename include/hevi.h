@@ -213,7 +213,8 @@ int hv_trace_read(hv_grid_t g, int32_t kind, double *ms_total, int64_t *launches
  * 8x2, 4x4); the damped short step keeps the default.  The column-fastest
  * slow flux has 12 more, c + 12: the same with each segment walking a run of
  * 8 columns along x, carrying the flux through the face it shares with the
- * next column (a block then spans 8 times the tile's columns along x).
+ * next column, in blocks of 1x16, 2x8 or 4x4 runs (shape 0..2; runs along x
+ * by rows).
  * Tile shape, block order and runs do not change any
  * result; neither does the mapping of the slow sweeps; the short step's
  * mapping sets how its column solve splits into in-lane elimination and

@@ -48,9 +48,12 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 // w = 1 the other width (see alt_seg).  i-fastest layout: w = 0 one lane per
 // column (64 columns per wavefront; single grids), w = 1 column segments of
 // the default width.  The column-fastest slow flux has 12 more, c + 12: the
-// same with every segment walking a run of kRun columns along x (a block
-// then covers kRun times the tile's columns along x).
+// same with every segment walking a run of kRun columns along x, in blocks
+// of 1x16, 2x8 or 4x4 runs (runs along x by rows), which keep the rows a
+// block reads around its own (its y-stencils) few.
 constexpr int kShapes[3] = {4, 3, 2};
+constexpr int kRunShapes[3] = {0, 1, 2};
+int shape_log2(int sh) { return sh < 3 ? kShapes[sh] : kRunShapes[sh - 3]; }   // sh 0..5
 constexpr int kConfigs = 24;   // most configurations of a kind
 constexpr int kRun = 8;
 enum { KIND_PREP = 0, KIND_FLUX = 1, KIND_SHORT = 2, NKIND = 3 };
@@ -204,7 +207,7 @@ size_t group_words(const std::vector<int> &ids, const hv_grid_desc *d)
     if (ids.size() > 1) {
         for (int s = 0; s < 6; ++s)
             for (int q : ids)
-                w += (size_t)hv::tiles_of_run(d[q].nx, d[q].ny, kShapes[s % 3], s < 3 ? 1 : kRun);
+                w += (size_t)hv::tiles_of_run(d[q].nx, d[q].ny, shape_log2(s), s < 3 ? 1 : kRun);
         for (int q : ids) w += (size_t)hv::partials_of(d[q].nx, d[q].ny);
     }
     return w;
@@ -435,7 +438,7 @@ hv::Group group_launch(const hv_ens *e, const GroupHost &g, int kind, int src, i
         const int sh = g.shape[kind] % 3, run = g.shape[kind] / 12;
         gr.blk = g.d_blk[sh + 3 * run];
         gr.nblocks = g.nblocks[sh + 3 * run];
-        gr.ti_log2 = kShapes[sh];
+        gr.ti_log2 = shape_log2(sh + 3 * run);
         gr.xcd = (g.shape[kind] / 3) % 2;
         gr.run = run ? kRun : 0;
         const bool w = (g.shape[kind] / 6) % 2;
@@ -744,7 +747,7 @@ int ens_create(hv_ens *e, int n, const hv_grid_desc *descs, void *ws, size_t byt
             g.nblocks[sh] = 0;
             if (nm > 1) g.d_blk[sh] = (unsigned *)dst + h.size();
             for (int a = 0; a < nm; ++a) {
-                const int nt = hv::tiles_of_run(e->m[g.ids[a]].nx, e->m[g.ids[a]].ny, kShapes[sh % 3],
+                const int nt = hv::tiles_of_run(e->m[g.ids[a]].nx, e->m[g.ids[a]].ny, shape_log2(sh),
                                                 sh < 3 ? 1 : kRun);
                 if (nt >= (1 << 24)) return fail(nullptr, HV_ERR_ARG, "member too large");
                 if (nm > 1)
@@ -1099,7 +1102,8 @@ void report_configs(const hv_ens *e, int32_t *tiles, int32_t *lanes, int32_t *ng
             const int c = g.shape[k];
             if (configs) configs[gi * NKIND + k] = c;
             if (tiles)
-                tiles[gi * NKIND + k] = ((c / 3) % 2 ? -1 : 1) * (1 << kShapes[c % 3]) * (c / 12 ? kRun : 1);
+                tiles[gi * NKIND + k] = ((c / 3) % 2 ? -1 : 1) * (1 << shape_log2(c % 3 + 3 * (c / 12))) *
+                                        (c / 12 ? kRun : 1);
             const bool w = (c / 6) % 2;
             int n = w ? alt_seg(e->prec, g.L) : default_seg(e->prec, g.L);
             if (e->layout == HV_IJK)

@@ -7,9 +7,10 @@
 // contiguous, so each per-lane access is one vector load and a wavefront
 // touches 4 (2) columns of contiguous memory.  Vertical neighbours live in the
 // adjacent lane of the same segment (DPP row shifts or shuffles); horizontal
-// neighbours are other columns and come through L1/L2.  A block covers a tile
-// of 16 columns (16x1, 8x2 or 4x4, in launch or XCD-chunked order, as the
-// autotuner chose; the results do not depend on it).
+// neighbours are other columns and come through L1/L2.  A tile of 16 columns
+// (16x1, 8x2 or 4x4, in launch or XCD-chunked order, as the autotuner chose;
+// the results do not depend on it) runs as one block, or as two blocks of 8
+// columns with 32-lane segments.
 //
 // The per-column tridiagonal system of the vertically implicit part is solved
 // without leaving the segment: every lane eliminates its interior rows in
@@ -64,13 +65,13 @@ struct Where {
 // whole group keep launch order.  Most x-neighbours then share an L2, while
 // all XCDs still stream through neighbouring memory at any moment (giving
 // each XCD one contiguous eighth of the domain instead was slower).  The
-// autotuner decides whether it pays.
+// autotuner decides whether it pays.  nblocks: blocks of the launch.
 constexpr int kXcdChunk = 8;
-__device__ __forceinline__ int block_order(const Group &gr)
+__device__ __forceinline__ int block_order(const Group &gr, int nblocks)
 {
     int b = (int)blockIdx.x;
     if (gr.xcd) {
-        const int full = gr.nblocks / (8 * kXcdChunk) * (8 * kXcdChunk);
+        const int full = nblocks / (8 * kXcdChunk) * (8 * kXcdChunk);
         if (b < full) {
             const int n = b >> 3;
             b = (n / kXcdChunk) * (8 * kXcdChunk) + (b & 7) * kXcdChunk + n % kXcdChunk;
@@ -79,11 +80,22 @@ __device__ __forceinline__ int block_order(const Group &gr)
     return b;
 }
 
+// Blocks per tile: a 32-lane segment's tile of 16 columns runs as two
+// blocks of 8 columns (256 threads each), so that resident blocks are not
+// the occupancy limit (512-thread blocks fit only 4 waves per SIMD where the
+// registers allow 5).  Launches multiply the grid by it.
+template <int SG>
+constexpr int split_of() { return SG == 32 ? 2 : 1; }
+template <int SG>
+constexpr int threads_of() { return kColsPerBlock / split_of<SG>() * SG; }
+
 template <int SG = SEG>
 __device__ __forceinline__ Where locate(const Group &gr)
 {
     Where w;
-    const int b = block_order(gr);
+    constexpr int sp = split_of<SG>();
+    const int b0 = block_order(gr, gr.nblocks * sp);
+    const int b = b0 / sp;
     int t = b, id = gr.first;
     if (gr.nm > 1) {
         const unsigned v = gr.blk[b];
@@ -93,7 +105,7 @@ __device__ __forceinline__ Where locate(const Group &gr)
     w.m = gr.mem + id;
     const int ti = 1 << gr.ti_log2, tj = kColsPerBlock >> gr.ti_log2;
     const int tiles_x = (w.m->nx + ti - 1) / ti;
-    const int c = (int)threadIdx.x / SG;
+    const int c = (int)threadIdx.x / SG + (b0 % sp) * (kColsPerBlock / sp);
     w.i = (t % tiles_x) * ti + (c & (ti - 1));
     w.j = (t / tiles_x) * tj + (c >> gr.ti_log2);
     w.active = w.i < w.m->nx && w.j < w.m->ny;
@@ -417,7 +429,7 @@ __device__ __forceinline__ void prep_body(
 }
 
 template <typename T, class Lay, int L, bool TR, int SG>
-__global__ __launch_bounds__(kColsPerBlock * SG) void k_slow_prep(Group gr)
+__global__ __launch_bounds__(threads_of<SG>()) void k_slow_prep(Group gr)
 {
     const Where wh = locate<SG>(gr);
     if (!wh.active) return;
@@ -768,7 +780,7 @@ template <typename T, class Lay, int L, bool TR>
 constexpr int flux_waves() { return (sizeof(T) == 4 && L == 4 && !TR && Lay::kContig) ? 4 : 1; }
 
 template <typename T, class Lay, int L, bool TR, int SG>
-__global__ __launch_bounds__(kColsPerBlock * SG)
+__global__ __launch_bounds__(threads_of<SG>())
 __attribute__((amdgpu_waves_per_eu(flux_waves<T, Lay, L, TR>())))
 void k_slow_flux(Group gr)
 {
@@ -801,7 +813,9 @@ template <int SG>
 __device__ __forceinline__ Where locate_run(const Group &gr)
 {
     Where w;
-    const int b = block_order(gr);
+    constexpr int sp = split_of<SG>();
+    const int b0 = block_order(gr, gr.nblocks * sp);
+    const int b = b0 / sp;
     int t = b, id = gr.first;
     if (gr.nm > 1) {
         const unsigned v = gr.blk[b];
@@ -812,7 +826,7 @@ __device__ __forceinline__ Where locate_run(const Group &gr)
     const int ti = 1 << gr.ti_log2, tj = kColsPerBlock >> gr.ti_log2;
     const int span = ti * gr.run;
     const int tiles_x = (w.m->nx + span - 1) / span;
-    const int c = (int)threadIdx.x / SG;
+    const int c = (int)threadIdx.x / SG + (b0 % sp) * (kColsPerBlock / sp);
     w.i = (t % tiles_x) * span + (c & (ti - 1)) * gr.run;
     w.j = (t / tiles_x) * tj + (c >> gr.ti_log2);
     w.active = w.i < w.m->nx && w.j < w.m->ny;
@@ -820,7 +834,7 @@ __device__ __forceinline__ Where locate_run(const Group &gr)
 }
 
 template <typename T, class Lay, int L, bool TR, int SG>
-__global__ __launch_bounds__(kColsPerBlock * SG)
+__global__ __launch_bounds__(threads_of<SG>())
 void k_slow_flux_run(Group gr)
 {
     const Where wh = locate_run<SG>(gr);
@@ -1621,12 +1635,11 @@ __device__ __forceinline__ void short_body(
     ln.store(tpo, tpn);
 }
 
-// SG lanes per column, kColsPerBlock columns per block of kColsPerBlock * SG
-// threads.
+// SG lanes per column, threads_of<SG>() / SG columns per block.
 // DP variants damp (members without damping data skip it) at the model time
 // sums[2] + offset * dt, the end of this short step.
 template <typename T, typename S, class Lay, int L, bool TR, bool EV, int SG, bool DP>
-__global__ __launch_bounds__(kColsPerBlock * SG)
+__global__ __launch_bounds__(threads_of<SG>())
 __attribute__((amdgpu_waves_per_eu(short_waves<T, S, L, TR, EV, SG, DP>())))
 void k_short_step(Group gr, double frac, double offset)
 {
@@ -1936,11 +1949,11 @@ struct RunPrep {
         return by_seg<T, L, Lay::kContig>(gr.seg, [&](auto sg, auto kl) {
             constexpr int SG = decltype(sg)::value, KL = decltype(kl)::value;
             if (gr.terrain)
-                hipLaunchKernelGGL((k_slow_prep<T, Lay, KL, true, SG>), dim3(gr.nblocks),
-                                   dim3(kColsPerBlock * SG), 0, s, gr);
+                hipLaunchKernelGGL((k_slow_prep<T, Lay, KL, true, SG>), dim3(gr.nblocks * split_of<SG>()),
+                                   dim3(threads_of<SG>()), 0, s, gr);
             else
-                hipLaunchKernelGGL((k_slow_prep<T, Lay, KL, false, SG>), dim3(gr.nblocks),
-                                   dim3(kColsPerBlock * SG), 0, s, gr);
+                hipLaunchKernelGGL((k_slow_prep<T, Lay, KL, false, SG>), dim3(gr.nblocks * split_of<SG>()),
+                                   dim3(threads_of<SG>()), 0, s, gr);
             return hipGetLastError();
         });
     }
@@ -1956,20 +1969,20 @@ struct RunFlux {
             if constexpr (Lay::kContig) {
                 if (gr.run > 1) {
                     if (gr.terrain)
-                        hipLaunchKernelGGL((k_slow_flux_run<T, A, KL, true, SG>), dim3(gr.nblocks),
-                                           dim3(kColsPerBlock * SG), 0, s, gr);
+                        hipLaunchKernelGGL((k_slow_flux_run<T, A, KL, true, SG>), dim3(gr.nblocks * split_of<SG>()),
+                                           dim3(threads_of<SG>()), 0, s, gr);
                     else
-                        hipLaunchKernelGGL((k_slow_flux_run<T, A, KL, false, SG>), dim3(gr.nblocks),
-                                           dim3(kColsPerBlock * SG), 0, s, gr);
+                        hipLaunchKernelGGL((k_slow_flux_run<T, A, KL, false, SG>), dim3(gr.nblocks * split_of<SG>()),
+                                           dim3(threads_of<SG>()), 0, s, gr);
                     return hipGetLastError();
                 }
             }
             if (gr.terrain)
-                hipLaunchKernelGGL((k_slow_flux<T, A, KL, true, SG>), dim3(gr.nblocks),
-                                   dim3(kColsPerBlock * SG), 0, s, gr);
+                hipLaunchKernelGGL((k_slow_flux<T, A, KL, true, SG>), dim3(gr.nblocks * split_of<SG>()),
+                                   dim3(threads_of<SG>()), 0, s, gr);
             else
-                hipLaunchKernelGGL((k_slow_flux<T, A, KL, false, SG>), dim3(gr.nblocks),
-                                   dim3(kColsPerBlock * SG), 0, s, gr);
+                hipLaunchKernelGGL((k_slow_flux<T, A, KL, false, SG>), dim3(gr.nblocks * split_of<SG>()),
+                                   dim3(threads_of<SG>()), 0, s, gr);
             return hipGetLastError();
         });
     }
@@ -1994,8 +2007,8 @@ struct RunShort {
     {
         return by_seg<T, L, Lay::kContig && !DP>(gr.seg, [&](auto sg, auto kl) {
             constexpr int SG = decltype(sg)::value, KL = decltype(kl)::value;
-            hipLaunchKernelGGL((k_short_step<T, S, A, KL, TR, EV, SG, DP>), dim3(gr.nblocks),
-                               dim3(kColsPerBlock * SG), 0, s, gr, frac, offset);
+            hipLaunchKernelGGL((k_short_step<T, S, A, KL, TR, EV, SG, DP>), dim3(gr.nblocks * split_of<SG>()),
+                               dim3(threads_of<SG>()), 0, s, gr, frac, offset);
             return hipGetLastError();
         });
     }

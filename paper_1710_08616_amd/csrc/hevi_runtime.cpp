@@ -1135,12 +1135,12 @@ int tune(hv_ens *e, int32_t *out, int32_t *lanes, int32_t *ngroups)
     int rc = HV_OK;
     for (auto &g : e->groups) {
         for (int kind = 0; kind < NKIND && rc == HV_OK; ++kind) {
-            // two interleaved rounds, the faster of each configuration's two
+            // three interleaved rounds, the fastest of each configuration's
             // timings counts (one round alone let run-to-run noise decide)
             const int nconf = configs_of(e, kind);
             float t[kConfigs];
             std::fill(t, t + kConfigs, 1e30f);
-            for (int it = 0; it < 2 * nconf && rc == HV_OK; ++it) {
+            for (int it = 0; it < 3 * nconf && rc == HV_OK; ++it) {
                 const int s = it % nconf;
                 g.shape[kind] = s;
                 // the slow arrays the flux and short step read must hold this stage's values
@@ -1148,7 +1148,7 @@ int tune(hv_ens *e, int32_t *out, int32_t *lanes, int32_t *ngroups)
                     (kind == KIND_SHORT && (r = launch(g, KIND_FLUX, e->stream)) != hipSuccess) ||
                     (r = launch(g, kind, e->stream)) != hipSuccess ||
                     (r = hipEventRecord(a, e->stream)) != hipSuccess) { rc = hip_fail(e, r, "tune"); break; }
-                for (int rep = 0; rep < 3; ++rep)
+                for (int rep = 0; rep < 4; ++rep)
                     if ((r = launch(g, kind, e->stream)) != hipSuccess) break;
                 if (r == hipSuccess) r = hipEventRecord(b, e->stream);
                 if (r == hipSuccess) r = hipEventSynchronize(b);

@@ -212,7 +212,7 @@ int hv_trace_read(hv_grid_t g, int32_t kind, double *ms_total, int64_t *launches
  * c = shape + 3 * chunked + 6 * other_width, 0..11 (shape 0..2 for 16x1,
  * 8x2, 4x4); the damped short step keeps the default.  The column-fastest
  * slow flux has 12 more, c + 12: the same with each segment walking a run of
- * 8 columns along x, carrying the flux through the face it shares with the
+ * 32 columns along x, carrying the flux through the face it shares with the
  * next column, in blocks of 1x16, 2x8 or 4x4 runs (shape 0..2; runs along x
  * by rows).
  * Tile shape, block order and runs do not change any

@@ -9,8 +9,8 @@
 // adjacent lane of the same segment (DPP row shifts or shuffles); horizontal
 // neighbours are other columns and come through L1/L2.  A tile of 16 columns
 // (16x1, 8x2 or 4x4, in launch or XCD-chunked order, as the autotuner chose;
-// the results do not depend on it) runs as one block, or as two blocks of 8
-// columns with 32-lane segments.
+// the results do not depend on it) runs as one block, or in the slow sweeps
+// with 32-lane segments as two blocks of 8 columns.
 //
 // The per-column tridiagonal system of the vertically implicit part is solved
 // without leaving the segment: every lane eliminates its interior rows in
@@ -80,20 +80,22 @@ __device__ __forceinline__ int block_order(const Group &gr, int nblocks)
     return b;
 }
 
-// Blocks per tile: a 32-lane segment's tile of 16 columns runs as two
-// blocks of 8 columns (256 threads each), so that resident blocks are not
-// the occupancy limit (512-thread blocks fit only 4 waves per SIMD where the
-// registers allow 5).  Launches multiply the grid by it.
+// Blocks per tile (SP): in the slow sweeps a 32-lane segment's tile of 16
+// columns runs as two blocks of 8 columns (256 threads each), so that
+// resident blocks are not the occupancy limit (512-thread blocks fit only 4
+// waves per SIMD where the registers allow 5; FP64 flux 1.67 -> 1.56 ms).
+// The short step keeps one block per tile (measured 1.77 ms against
+// 1.78-1.79 ms split).  Launches multiply the grid by it.
 template <int SG>
 constexpr int split_of() { return SG == 32 ? 2 : 1; }
-template <int SG>
-constexpr int threads_of() { return kColsPerBlock / split_of<SG>() * SG; }
+template <int SG, int SP = split_of<SG>()>
+constexpr int threads_of() { return kColsPerBlock / SP * SG; }
 
-template <int SG = SEG>
+template <int SG = SEG, int SP = split_of<SG>()>
 __device__ __forceinline__ Where locate(const Group &gr)
 {
     Where w;
-    constexpr int sp = split_of<SG>();
+    constexpr int sp = SP;
     const int b0 = block_order(gr, gr.nblocks * sp);
     const int b = b0 / sp;
     int t = b, id = gr.first;
@@ -1635,15 +1637,16 @@ __device__ __forceinline__ void short_body(
     ln.store(tpo, tpn);
 }
 
-// SG lanes per column, threads_of<SG>() / SG columns per block.
+// SG lanes per column, kColsPerBlock columns per block of kColsPerBlock * SG
+// threads.
 // DP variants damp (members without damping data skip it) at the model time
 // sums[2] + offset * dt, the end of this short step.
 template <typename T, typename S, class Lay, int L, bool TR, bool EV, int SG, bool DP>
-__global__ __launch_bounds__(threads_of<SG>())
+__global__ __launch_bounds__((threads_of<SG, 1>()))
 __attribute__((amdgpu_waves_per_eu(short_waves<T, S, L, TR, EV, SG, DP>())))
 void k_short_step(Group gr, double frac, double offset)
 {
-    const Where wh = locate<SG>(gr);
+    const Where wh = locate<SG, 1>(gr);
     if (!wh.active) return;
     const MemberDev *m = wh.m;
     const Lane<Lay, L, SG> ln(m->nx, m->ny, m->nz, wh.i, wh.j);
@@ -2007,8 +2010,8 @@ struct RunShort {
     {
         return by_seg<T, L, Lay::kContig && !DP>(gr.seg, [&](auto sg, auto kl) {
             constexpr int SG = decltype(sg)::value, KL = decltype(kl)::value;
-            hipLaunchKernelGGL((k_short_step<T, S, A, KL, TR, EV, SG, DP>), dim3(gr.nblocks * split_of<SG>()),
-                               dim3(threads_of<SG>()), 0, s, gr, frac, offset);
+            hipLaunchKernelGGL((k_short_step<T, S, A, KL, TR, EV, SG, DP>), dim3(gr.nblocks),
+                               dim3(threads_of<SG, 1>()), 0, s, gr, frac, offset);
             return hipGetLastError();
         });
     }

@@ -55,7 +55,7 @@ constexpr int kShapes[3] = {4, 3, 2};
 constexpr int kRunShapes[3] = {0, 1, 2};
 int shape_log2(int sh) { return sh < 3 ? kShapes[sh] : kRunShapes[sh - 3]; }   // sh 0..5
 constexpr int kConfigs = 24;   // most configurations of a kind
-constexpr int kRun = 8;
+constexpr int kRun = 32;
 enum { KIND_PREP = 0, KIND_FLUX = 1, KIND_SHORT = 2, NKIND = 3 };
 
 struct MemberHost {

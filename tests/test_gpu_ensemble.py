@@ -76,8 +76,8 @@ def test_tuned_tile_shapes_give_identical_results(hv, tmp_path, monkeypatch):
     e0.close()
     e1 = hv.Ensemble(ms, precision="fp32")
     shapes = e1.tune()
-    # tile x-extents: 16, 8 or 4 columns, or 1, 2 or 4 runs of 8 columns (slow flux)
-    assert len(shapes) == 2 and all(abs(x) in (16, 8, 4, 32)
+    # tile x-extents: 16, 8 or 4 columns, or 1, 2 or 4 runs of 32 columns (slow flux)
+    assert len(shapes) == 2 and all(abs(x) in (16, 8, 4, 32, 64, 128)
                                     for tiles, _ in shapes for x in tiles)
     assert all(n in (8, 16, 32) for _, lanes in shapes for n in lanes)
     # the short step's width changes its rounding; every other choice is bitwise
@@ -93,7 +93,7 @@ def test_tuned_tile_shapes_give_identical_results(hv, tmp_path, monkeypatch):
 def test_every_launch_configuration_is_bitwise(hv, tmp_path, monkeypatch):
     """Each launch configuration of the slow sweeps (three tile shapes, launch
     order or XCD-chunked order, 16 or 8 lanes per column; for the flux also
-    in runs of 8 columns along x) and each of the short step's six at its
+    in runs of 32 columns along x) and each of the short step's six at its
     default width, forced through the tune cache read at creation, gives the
     untuned result bitwise.  90 16x1 tiles (75 8x2, 80 4x4): the chunked
     order deals 64 of them and leaves the rest in launch order; two members

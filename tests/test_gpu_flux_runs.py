@@ -1,5 +1,5 @@
 """The slow flux in runs along x (hv_configure flux configurations 12..23,
-column-fastest layout): every segment walks 8 consecutive columns and
+column-fastest layout): every segment walks RUN = 32 consecutive columns and
 carries the flux through the face it shares with the next column, with the
 x-window of the advected quantities, instead of evaluating both x-faces of
 every column.  Each face flux takes the same operands in the same order as
@@ -15,6 +15,8 @@ import pytest
 from paper_1710_08616_amd import inputs
 
 pytestmark = pytest.mark.gpu
+
+RUN = 32   # columns per run
 
 
 @pytest.fixture(scope="module")
@@ -56,8 +58,8 @@ def test_flux_in_runs_is_bitwise_equal(hv, prec, nz, terrain):
     for base_c, run_c in ((5, 17), (0, 12), (10, 22)):
         ref, t0 = _run(hv, s, prec, [5, base_c, 5])
         got, t1 = _run(hv, s, prec, [5, run_c, 5])
-        # blocks of 1x16, 2x8 or 4x4 runs of 8 columns
-        assert abs(t1[1]) == 8 * {16: 1, 8: 2, 4: 4}[abs(t0[1])]
+        # blocks of 1x16, 2x8 or 4x4 runs of 32 columns
+        assert abs(t1[1]) == RUN * {16: 1, 8: 2, 4: 4}[abs(t0[1])]
         for name, a, b in zip(inputs.FIELD_NAMES, got, ref):
             assert np.array_equal(a, b), (name, base_c, run_c)
 

@@ -1797,6 +1797,47 @@ __global__ __launch_bounds__(BLOCK) void k_sum_partial(Group gr)
     if (threadIdx.x == 0) (gr.part ? gr.part : m->partials)[q] = s;
 }
 
+// Mass partials in the i-fastest layout: one lane per column, consecutive
+// lanes at consecutive columns of the (i, j) plane, so every level is one
+// coalesced row per wavefront (the segment form above loads a lane's levels
+// one row of nx * ny apart).  Partial block q takes the member's chunks of
+// BLOCK columns q, q + P, q + 2P, ... (P = its partial count) in that order,
+// each lane summing its column bottom to top in float64, then the fixed tree
+// over the block.
+template <typename T, bool TR>
+__global__ __launch_bounds__(BLOCK) void k_sum_mass_cols(Group gr)
+{
+    __shared__ double sh[BLOCK];
+    int q = (int)blockIdx.x, id = gr.first;
+    if (gr.nm > 1) {
+        const unsigned v = gr.blk[blockIdx.x];
+        q = (int)(v & 0xFFFFFFu);
+        id = (int)(v >> 24);
+    }
+    const MemberDev *m = gr.mem + id;
+    const int ncol = m->nx * m->ny, nz = m->nz;
+    const int nchunk = (ncol + BLOCK - 1) / BLOCK;
+    const double *__restrict__ vol = m->vm + (size_t)VM_VOL * nz;
+    const T *__restrict__ r = (const T *)buf(m, gr.src, 0);
+    double acc = 0.0;
+    for (int t = q; t < nchunk; t += m->npart) {
+        const int c = t * BLOCK + (int)threadIdx.x;
+        if (c < ncol) {
+            double jc = 1.0;
+            if constexpr (TR) jc = m->geo[(size_t)c * GEO_NFIELDS + GEO_J];
+            const T *__restrict__ rc = r + c;
+#pragma unroll 8
+            for (int k = 0; k < nz; ++k) {
+                double v = vol[k];
+                if constexpr (TR) v = v * jc;
+                acc += (double)__builtin_nontemporal_load(rc + (size_t)k * ncol) * v;
+            }
+        }
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) (gr.part ? gr.part : m->partials)[q] = s;
+}
+
 // One block per member of the group: sum its partials in a fixed order
 // (thread t takes t, t + BLOCK, ... with Neumaier compensation, then a tree).
 __global__ __launch_bounds__(BLOCK) void k_sum_final(Group gr, int slot)
@@ -2086,6 +2127,20 @@ hipError_t launch_short_step(int prec, int layout, int L, const Group &gr, doubl
 
 hipError_t launch_sums(int prec, int layout, int L, const Group &gr, bool energy, hipStream_t s)
 {
+    if (layout == 0 && !energy) {
+        // the i-fastest layout's mass: one lane per column (coalesced rows)
+        if (prec == 0) {
+            if (gr.terrain) hipLaunchKernelGGL((k_sum_mass_cols<double, true>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr);
+            else hipLaunchKernelGGL((k_sum_mass_cols<double, false>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr);
+        } else if (prec == 1 || prec == 2) {
+            if (gr.terrain) hipLaunchKernelGGL((k_sum_mass_cols<float, true>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr);
+            else hipLaunchKernelGGL((k_sum_mass_cols<float, false>), dim3(gr.nblocks), dim3(BLOCK), 0, s, gr);
+        } else {
+            return hipErrorInvalidValue;
+        }
+        hipLaunchKernelGGL(k_sum_final, dim3(gr.nm), dim3(BLOCK), 0, s, gr, 0);
+        return hipGetLastError();
+    }
     return dispatch<RunSums>(prec, layout, L, gr, energy, s);
 }
 

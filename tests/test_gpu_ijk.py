@@ -128,3 +128,47 @@ def test_column_graph_replay_equals_direct_launches(hv):
         d.close()
     for a, b in zip(*out):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
+@pytest.mark.parametrize("nx,ny,nz,terrain", [(70, 9, 64, False), (37, 23, 32, True), (300, 5, 128, False)])
+def test_column_mass_matches_the_oracle_and_the_segment_sum(hv, oracle, prec, nx, ny, nz, terrain):
+    """The i-fastest mass sum (one lane per column; 630, 851 and 1500
+    columns: chunks of 256 with a ragged last one) equals the oracle's mass of
+    the device state and the column-fastest layout's segment sum of the same
+    state to 1e-14 (float64 sums in another order), after steps and at
+    state_init; an ensemble of i-fastest members (grouped launch) gives each
+    member's single-grid mass bitwise."""
+    s = _state(nx, ny, nz, terrain, 90 + nx)
+    print(f"case: ijk mass sum {prec} {nx}x{ny}x{nz} terrain={terrain}", flush=True)
+    d = hv.Domain(s, precision=prec, layout="ijk")
+    m_init = d.mass()
+    d.step(s.dt, 1, s.n_short)
+    m = d.mass()
+    s2 = s.copy()
+    s2.fields = d.read_all()
+    d.close()
+    want = oracle.mass(s2)
+    assert abs(m - want) <= 1e-14 * abs(want), (m, want)
+    k = hv.Domain(s2, precision=prec, layout="kij")
+    mk = k.mass()
+    k.close()
+    assert abs(m - mk) <= 1e-14 * abs(mk), (m, mk)
+    s0 = s.as_f32() if prec != "fp64" else s
+    assert abs(m_init - oracle.mass(s0)) <= 1e-14 * abs(m_init)
+
+
+def test_column_mass_in_an_ensemble_equals_single_grids(hv):
+    ms = [_state(70, 9, 64, False, 95), _state(37, 23, 64, False, 96), _state(20, 30, 64, False, 97)]
+    print("case: ijk mass ensemble", flush=True)
+    e = hv.Ensemble(ms, precision="fp32", layout="ijk")
+    e.step(1, 3)
+    got = [e.mass(q) for q in range(len(ms))]
+    states = [e.read_all(q) for q in range(len(ms))]
+    e.close()
+    for q, s in enumerate(ms):
+        s2 = s.copy()
+        s2.fields = states[q]
+        d = hv.Domain(s2, precision="fp32", layout="ijk")
+        assert d.mass() == got[q], q
+        d.close()

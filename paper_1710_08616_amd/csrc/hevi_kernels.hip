@@ -2057,16 +2057,17 @@ struct RunShort {
         });
     }
     // 32-bit offsets: with global instructions in the flat, undamped
-    // float-storage step (measured on 1024 x 1024 x 64: 0.895 -> 0.876 ms;
-    // the Runge-Kutta pair unchanged; the damped form loses 4%), with flat
-    // instructions in the undamped terrain step (over hills, 1600 x 1280 x
-    // 64: mixed 2.028 -> 1.974-2.008 ms, FP64 3.70 -> 3.64 ms; global ones
-    // 2.00 and 3.74 ms)
+    // float32 step (measured on 1024 x 1024 x 64: 0.895 -> 0.876 ms; the
+    // Runge-Kutta pair unchanged; the damped form loses 4%), with flat
+    // instructions in the flat mixed step (global 0.915, flat 0.903 ms) and
+    // in the undamped terrain step (over hills, 1600 x 1280 x 64: mixed
+    // 2.028 -> 1.974-2.008 ms, FP64 3.70 -> 3.64 ms; global ones 2.00 and
+    // 3.74 ms)
     template <bool TR, bool EV, bool DP>
     static hipError_t go(const Group &gr, double frac, double offset, hipStream_t s)
     {
         if constexpr (sizeof(T) == 4 && !TR && !DP) {
-            if (gr.off32) return launch<Off32<Lay, true>, TR, EV, DP>(gr, frac, offset, s);
+            if (gr.off32) return launch<Off32<Lay, (sizeof(S) == 4)>, TR, EV, DP>(gr, frac, offset, s);
         }
         if constexpr (TR && !DP) {
             if (gr.off32) return launch<Off32<Lay, false>, TR, EV, DP>(gr, frac, offset, s);

@@ -2032,9 +2032,13 @@ struct RunFlux {
     }
     // The slow flux is instruction-heavy enough that 32-bit array offsets pay
     // (float32: 0.973 -> 0.895 ms, float64: 2.50 -> 2.09 ms on 1024x1024x64);
-    // the host selects them when every array fits in 4 GiB.
+    // the host selects them when every array fits in 4 GiB.  Global
+    // instructions for the float64 flux and for the runs (float32 runs: 0.80
+    // -> 0.77 ms; float64 runs with flat ones 1.52 -> 1.55 ms), flat ones for
+    // the per-column float flux.
     static hipError_t run(const Group &gr, hipStream_t s)
     {
+        if (gr.off32 && gr.run > 1) return go<Off32<Lay, true>>(gr, s);
         if (gr.off32) return go<Off32<Lay, sizeof(T) == 8>>(gr, s);
         return go<Lay>(gr, s);
     }

@@ -2066,7 +2066,8 @@ struct RunShort {
     // instructions in the flat mixed step (global 0.915, flat 0.903 ms) and
     // in the undamped terrain step (over hills, 1600 x 1280 x 64: mixed
     // 2.028 -> 1.974-2.008 ms, FP64 3.70 -> 3.64 ms; global ones 2.00 and
-    // 3.74 ms)
+    // 3.74 ms); with global instructions in the flat FP64 step (4x4 tiles,
+    // chunked: 1.766 -> 1.754 ms; 1.8-3.7% in the other configurations)
     template <bool TR, bool EV, bool DP>
     static hipError_t go(const Group &gr, double frac, double offset, hipStream_t s)
     {
@@ -2075,6 +2076,9 @@ struct RunShort {
         }
         if constexpr (TR && !DP) {
             if (gr.off32) return launch<Off32<Lay, false>, TR, EV, DP>(gr, frac, offset, s);
+        }
+        if constexpr (sizeof(T) == 8 && !TR && !DP) {
+            if (gr.off32) return launch<Off32<Lay, true>, TR, EV, DP>(gr, frac, offset, s);
         }
         return launch<Lay, TR, EV, DP>(gr, frac, offset, s);
     }

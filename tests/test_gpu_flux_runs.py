@@ -90,3 +90,22 @@ def test_flux_in_runs_in_an_ensemble(hv):
     for q in range(len(ms)):
         for name, a, b in zip(inputs.FIELD_NAMES, out[15][q], out[3][q]):
             assert np.array_equal(a, b), (q, name)
+
+
+def test_run_configurations_exist_for_the_column_fastest_flux_only(hv):
+    """Configurations 12..23 are the column-fastest flux's; the other kinds,
+    and every kind of the i-fastest layout, take 0..11 (HV_ERR_ARG beyond)."""
+    s = _state(20, 12, 32, False, seed=91)
+    print("case: flux run configuration range", flush=True)
+    d = hv.Domain(s, precision="fp32")
+    assert d.configure([0, 23, 0])[0] == [0, 23, 0]
+    for bad in ([12, 0, 0], [0, 0, 12], [0, 24, 0], [0, -1, 0]):
+        with pytest.raises(hv.HvError) as e:
+            d.configure(bad)
+        assert e.value.code == hv.HV_ERR_ARG
+    d.close()
+    d = hv.Domain(s, precision="fp32", layout="ijk")
+    with pytest.raises(hv.HvError) as e:
+        d.configure([0, 12, 0])
+    assert e.value.code == hv.HV_ERR_ARG
+    d.close()

@@ -99,6 +99,9 @@ struct Group {
     int seg;                // lanes per column (8, 16, 32; 0: the default)
     int colmap;             // i-fastest layout, one member: one lane per column
     int nx1, ny1;           // columns of the member when nm == 1
+    int rev;                // 1: blocks take the tiles in reverse order (each launch
+                            // starts where the previous one ended, whose data the
+                            // caches still hold)
     int run;                // slow flux, column-fastest layout: > 1 = columns per
                             // segment run along x (blocks cover runs, see
                             // tiles_of_run); else one column per segment

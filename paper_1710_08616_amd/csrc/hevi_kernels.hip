@@ -77,7 +77,7 @@ __device__ __forceinline__ int block_order(const Group &gr, int nblocks)
             b = (n / kXcdChunk) * (8 * kXcdChunk) + (b & 7) * kXcdChunk + n % kXcdChunk;
         }
     }
-    return b;
+    return gr.rev ? nblocks - 1 - b : b;
 }
 
 // Blocks per tile (SP): in the slow sweeps a 32-lane segment's tile of 16

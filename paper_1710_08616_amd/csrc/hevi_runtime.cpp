@@ -507,10 +507,20 @@ hipError_t enqueue_long_step(hv_ens *e, int n_short, const int r[3], hipStream_t
     const double frac[3] = {1.0 / 3.0, 0.5, 1.0};
     const int P = r[0], R[2] = {r[1], r[2]};
     hipError_t err = hipSuccess;
+    // Successive launches of a group take its tiles in alternating
+    // directions, so that each starts on the tiles whose data the previous
+    // one touched last (still in the Infinity Cache and the L2s).
+    std::vector<int> dir(e->groups.size(), 0);
+    auto flip = [&](const GroupHost &g, hv::Group gr) {
+        int &d = dir[&g - e->groups.data()];
+        gr.rev = d;
+        d ^= 1;
+        return gr;
+    };
     for (int st = 0; st < 3; ++st) {
         const int in = st == 0 ? P : R[(n_short - 1) & 1];
         for (auto &g : e->groups) {
-            const hv::Group gp = group_launch(e, g, KIND_PREP, in), gf = group_launch(e, g, KIND_FLUX, in);
+            const hv::Group gp = flip(g, group_launch(e, g, KIND_PREP, in)), gf = flip(g, group_launch(e, g, KIND_FLUX, in));
             err = traced(e, s, HV_K_SLOW_PREP, [&] { return hv::launch_slow_prep(e->prec, e->layout, g.L, gp, s); });
             if (err != hipSuccess) return err;
             err = traced(e, s, HV_K_SLOW_FLUX, [&] { return hv::launch_slow_flux(e->prec, e->layout, g.L, gf, s); });
@@ -525,18 +535,18 @@ hipError_t enqueue_long_step(hv_ens *e, int n_short, const int r[3], hipStream_t
             for (auto &g : e->groups) {
                 if (e->rk2) {
                     // X* = Phi(X, X, dtau/2) into buffer 3, then X+ = Phi(X, X*, dtau)
-                    const hv::Group g1 = group_launch(e, g, KIND_SHORT, src, 3);
+                    const hv::Group g1 = flip(g, group_launch(e, g, KIND_SHORT, src, 3));
                     err = traced(e, s, HV_K_SHORT_STEP, [&] {
                         return hv::launch_short_step(e->prec, e->layout, g.L, g1, 0.5 * f, 0.0, s);
                     });
                     if (err != hipSuccess) return err;
-                    hv::Group g2 = group_launch(e, g, KIND_SHORT, src, dst, 3);
+                    hv::Group g2 = flip(g, group_launch(e, g, KIND_SHORT, src, dst, 3));
                     g2.damp = g.damping ? 1 : 0;
                     err = traced(e, s, HV_K_SHORT_STEP, [&] {
                         return hv::launch_short_step(e->prec, e->layout, g.L, g2, f, off, s);
                     });
                 } else {
-                    hv::Group gs = group_launch(e, g, KIND_SHORT, src, dst);
+                    hv::Group gs = flip(g, group_launch(e, g, KIND_SHORT, src, dst));
                     gs.damp = g.damping ? 1 : 0;
                     err = traced(e, s, HV_K_SHORT_STEP, [&] {
                         return hv::launch_short_step(e->prec, e->layout, g.L, gs, f, off, s);
